@@ -1,0 +1,172 @@
+"""Throughput benchmark of the q-LSKUM pseudo-time iteration on one MI355X.
+
+Workload: O-type cloud of 1250 x 2000 = 2.5M points around NACA 0012
+(cubic-Hermite O-grid, 5 x 5 lattice-box stencils, interior points jittered
+by U(-0.1, 0.1) local spacings, splitmix64 seed 2108), Hilbert-reordered;
+M 0.85, alpha 1 deg, Venkatakrishnan limiter K = 5, CFL 0.2, 3 inner
+iterations, FP64.  A step is one pseudo-time iteration (local time step,
+four Runge-Kutta stages of q-derivatives + flux residual + update, residual
+norm).  The state is resident in HBM before the timed region starts.
+
+Prints one JSON line (see the repository's measurement notes for the
+roofline and CPU-baseline definitions).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+NS, NR = 1250, 2000
+FLOW = dict(mach=0.85, alpha_deg=1.0, limiter=1, venkat_k=5.0, cfl=0.2, n_inner=3)
+FP64_VALU_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak
+
+# Algorithmic FP64 operations of the flux-residual kernel, per neighbour
+# entry that enters at least one split stencil, and per split stencil it
+# enters; transcendentals and divides are counted at a fixed operation
+# cost (exp 20, log 20, erfc 30, sqrt 10, divide 10).
+FLOPS_ENTRY_COMMON = 202       # geometry, reconstruction, two q~ -> primitive states
+FLOPS_ENTRY_LIMITER = 125      # Venkatakrishnan factors of 8 increments, eps^2
+FLOPS_PER_STENCIL = 191        # two split fluxes, their difference, weighted sum
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def flux_flops_per_launch(flags, kind, ptr, limiter):
+    """Algorithmic FP64 operations of one flux-residual launch, from the
+    library's split-membership flags (walls drop their n+ stencil; outer
+    points carry no residual)."""
+    npt = kind.shape[0]
+    owner = np.repeat(np.arange(npt), np.diff(ptr))
+    f = flags.astype(np.int64)
+    f = np.where(kind[owner] == 1, f & ~4, f)
+    f = np.where(kind[owner] == 2, 0, f)
+    used = f != 0
+    stencils = ((f & 3) != 0).astype(np.int64) + ((f & 12) != 0).astype(np.int64)
+    common = FLOPS_ENTRY_COMMON + (FLOPS_ENTRY_LIMITER if limiter else 0)
+    return int(used.sum()) * common + int(stencils.sum()) * FLOPS_PER_STENCIL
+
+
+def cpu_baseline(cloud, seconds_hint=30.0):
+    """Oracle (single thread, as it stands) on a bounded sample of the same
+    workload: one stage evaluation (q, 3 inner iterations, flux residual) of
+    the full cloud from the freestream start; an iteration is four stages."""
+    import oracle
+    o = oracle.Oracle(cloud, oracle.params(**FLOW))
+    U = o.freestream()
+    t0 = time.perf_counter()
+    o.evaluate(U)
+    t = time.perf_counter() - t0
+    return {"value": cloud.n / (4.0 * t) / 1e6, "unit": "Mpoint-iter/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"one stage evaluation of the full {cloud.n}-point cloud "
+                      f"({t:.1f} s single-threaded); iteration = 4 stages"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is a design note, not a built path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from cloudgen import naca_ocloud
+    from paper_2108_07031_amd import qlskum as ql
+
+    t0 = time.perf_counter()
+    cloud = naca_ocloud(NS, NR, jitter=0.1, seed=2108)
+    log(f"cloud {cloud.n} points, {cloud.nnz} entries ({time.perf_counter() - t0:.1f} s)")
+
+    torch.cuda.init()
+    stream = torch.cuda.Stream()  # default priority
+    torch.cuda.set_stream(stream)
+    s = ql.Solver(cloud, stream=stream, **FLOW)
+    flags = s.flags()
+    flops = flux_flops_per_launch(flags, cloud.kind, cloud.nbr_ptr, FLOW["limiter"])
+    s.init_freestream()
+    log("warmup")
+    s.step(args.warmup, want_history=False)
+
+    ql.ql_set_timing(s.h, 1)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    log(f"timed: {args.steps} iterations")
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    hist = s.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ktime = {k: ql.ql_kernel_time(s.h, k) for k in range(4)}
+    ql.ql_set_timing(s.h, 0)
+    log(f"wall {wall:.3f} s, events {gpu_ms / 1e3:.3f} s, residual {hist[0, 0]:.3e} -> "
+        f"{hist[-1, 0]:.3e}")
+    for k, name in enumerate(("grad0", "gradk", "flux", "resnorm")):
+        ms, cnt = ktime[k]
+        log(f"  {name}: {cnt} launches, avg {ms / max(cnt, 1) * 1e3:.1f} us, "
+            f"share {ms / gpu_ms * 100:.1f}%")
+    cl, cd = s.forces()
+    s.close()
+
+    elapsed = max(wall, gpu_ms / 1e3)
+    value = cloud.n * args.steps / elapsed / 1e6
+    flux_ms, flux_cnt = ktime[2]
+    flux_avg_s = flux_ms / max(flux_cnt, 1) / 1e3
+    achieved = flops / flux_avg_s / 1e12
+    out = {
+        "metric": "Mpoint-iter/s at 2.5M pts, FP64 vs mixed; time to 1e-6 residual, warm vs cold",
+        "value": value,
+        "unit": "Mpoint-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "q-LSKUM FP64, NACA 0012 O-cloud 1250x2000 (2.5M pts), jitter 0.1 "
+                        "seed 2108, Hilbert order, M 0.85, alpha 1, Venkatakrishnan K 5, "
+                        "CFL 0.2, 3 inner iterations",
+            "n_points": cloud.n,
+            "nnz": cloud.nnz,
+            "precision": "fp64",
+        },
+        "roofline": {
+            "kernel": "k_flux (flux residual + RK stage)",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP64_VALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_VALU_PEAK_TFLOPS,
+            "traffic": None,
+            "flops_per_launch": flops,
+            "avg_launch_us": flux_avg_s * 1e6,
+        },
+        "residual_first_last": [float(hist[0, 0]), float(hist[-1, 0])],
+        "cl_cd": [cl, cd],
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, one stage of the full cloud)")
+        out["cpu_baseline"] = cpu_baseline(cloud)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -201,7 +201,7 @@ def naca_ocloud(ns, nr, tau=0.12, r_outer=15.0, q_stretch=1.08 ** 59,
     NXf, NYf = NX.reshape(-1).copy(), NY.reshape(-1).copy()
     kindf = kind.reshape(-1)
     if stencil == "box":
-        ptr, idx = lattice_box_neighbours(x, y, ns, nr, box_halfwidth, max_neighbours, key)
+        ptr, idx = lattice_box_neighbours(x, y, ns, nr, box_halfwidth, max_neighbours)
         ptr, idx = enrich_half_planes(x, y, NXf, NYf, kindf, ptr, idx, max_neighbours)
     elif stencil == "radius":
         h_p = np.maximum.reduce([et_next, et_prev, er_next, er_prev])
@@ -349,42 +349,41 @@ def _in_half(v, h):
         return dn * dn > tie and dn < 0
     return dn * dn > tie and dn > 0
 
-def lattice_box_neighbours(x, y, ns, nr, k, cap, tie_key):
+def lattice_box_neighbours(x, y, ns, nr, k, cap, tie_key=None):
     """Neighbours of lattice point (i, j): every (i+a mod ns, j+b) with
-    |a|, |b| <= k, b inside the layer range, sorted by distance then by
-    `tie_key`; at most `cap` (the nearest, strictly closer than the first
-    one dropped)."""
+    |a|, |b| <= k, b inside the layer range, sorted by distance, ties by layer
+    offset b and then by the station offset a signed by the side of the
+    x axis the point lies on (so mirror images list mirrored neighbours in
+    the same order); at most `cap` (those strictly closer than the first one
+    dropped)."""
     n = ns * nr
-    offs = [(a, b) for b in range(-k, k + 1) for a in range(-k, k + 1) if (a, b) != (0, 0)]
     p = np.arange(n)
     ip, jp = p % ns, p // ns
-    rows, cols = [], []
-    for a, b in offs:
-        jn = jp + b
-        ok = (jn >= 0) & (jn < nr)
-        rows.append(p[ok])
-        cols.append(jn[ok] * ns + (ip[ok] + a) % ns)
-    rows = np.concatenate(rows)
-    cols = np.concatenate(cols)
-    dx = x[cols] - x[rows]
-    dy = y[cols] - y[rows]
-    d2 = dx * dx + dy * dy
-    k1, k2 = tie_key(rows, cols)
-    o = np.lexsort((k2, k1, d2, rows))
-    rows, cols, d2 = rows[o], cols[o], d2[o]
-    counts = np.bincount(rows, minlength=n)
+    side = np.where(y < 0.0, -1, 1)
+    offs = np.array([(a, b) for b in range(-k, k + 1) for a in range(-k, k + 1) if (a, b) != (0, 0)])
+    m = offs.shape[0]
+    # per side, offsets pre-ordered by the tie key (b, side * a)
+    order_up = np.lexsort((offs[:, 0], offs[:, 1]))
+    order_lo = np.lexsort((-offs[:, 0], offs[:, 1]))
+    A = np.where(side[:, None] > 0, offs[order_up, 0][None, :], offs[order_lo, 0][None, :])
+    B = np.where(side[:, None] > 0, offs[order_up, 1][None, :], offs[order_lo, 1][None, :])
+    jn = jp[:, None] + B
+    valid = (jn >= 0) & (jn < nr)
+    cols = np.where(valid, jn, 0) * ns + (ip[:, None] + A) % ns
+    dx = x[cols] - x[:, None]
+    dy = y[cols] - y[:, None]
+    d2 = np.where(valid, dx * dx + dy * dy, np.inf)
+    o = np.argsort(d2, axis=1, kind="stable")
+    d2 = np.take_along_axis(d2, o, axis=1)
+    cols = np.take_along_axis(cols, o, axis=1)
+    keep = np.isfinite(d2)
+    if m > cap:
+        cut = d2[:, cap][:, None]
+        keep &= ~np.isfinite(cut) | (d2 < cut)
+    counts = keep.sum(axis=1)
     ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=ptr[1:])
-    if counts.max() > cap:
-        keep = np.ones(rows.shape[0], dtype=bool)
-        for q in np.flatnonzero(counts > cap):
-            lo, hi = ptr[q], ptr[q + 1]
-            cut = d2[lo + cap]
-            keep[lo:hi] = d2[lo:hi] < cut
-        rows, cols = rows[keep], cols[keep]
-        counts = np.bincount(rows, minlength=n)
-        np.cumsum(counts, out=ptr[1:])
-    return ptr.astype(np.int32), cols.astype(np.int32)
+    return ptr.astype(np.int32), cols[keep].astype(np.int32)
 
 
 def _mirror_tie_key(ii, jj, ns, y):

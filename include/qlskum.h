@@ -1,0 +1,193 @@
+/*
+ * qlskum.h -- C ABI of the MI355X (gfx950) q-LSKUM solver library.
+ *
+ * The library advances the 2D Euler equations on a point cloud with the
+ * q-LSKUM meshfree scheme of "On the performance of GPU accelerated q-LSKUM
+ * based meshfree solvers in Fortran, C++, Python, and Julia" (Scientific
+ * Computing Report 01:2021): per pseudo-time iteration a local time step,
+ * then four Runge-Kutta stages of q-variables (sec. 2.1 eq. (26)),
+ * least-squares q-derivatives with inner iterations (eq. (29)), the
+ * kinetic split-flux residual over the four split stencils (eqs. (12)-(14),
+ * (27)-(28)) and the state update, then the residual norm (sec. 3,
+ * Algorithm 1).  Every step runs in the library's HIP kernels.
+ *
+ * Conventions (all entry points):
+ *  - Return an int status (QL_OK or a negative QL_E* code); no call aborts
+ *    the process.  ql_last_error() gives a message naming the point
+ *    (user numbering) or the argument at fault.
+ *  - Sizes are int64_t.  Per-point vectors are component-major ("SoA"):
+ *    U[c * n + p], c = 0..3 for (rho, rho u1, rho u2, rho e), p in the
+ *    caller's point order.  The library reorders points internally for
+ *    memory locality; callers always see their own order.
+ *  - Host pointers are borrowed for the duration of the call and copied.
+ *    Device pointers (mem = 1) must be device memory on the solver's
+ *    device (for example a torch tensor's data_ptr()); they are read or
+ *    written in stream order on the solver's stream and must stay valid
+ *    until the call returns.
+ *  - The library owns every solver buffer.  One solver per host thread;
+ *    solvers on one device may share a stream.
+ *  - After QL_EDEVICE the solver is poisoned: only ql_destroy and
+ *    ql_last_error remain valid.  Calls out of order (a step before an
+ *    upload, for example) return QL_ESTATE.
+ */
+#ifndef QLSKUM_H
+#define QLSKUM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ql_solver ql_solver;
+
+enum {
+    QL_OK = 0,
+    QL_EINVAL = -1,      /* bad argument or malformed cloud                   */
+    QL_ESINGULAR = -2,   /* a least-squares matrix the scheme inverts is singular */
+    QL_ENOMEM = -3,      /* device or host allocation failed                  */
+    QL_EDEVICE = -4,     /* HIP runtime error; solver poisoned                */
+    QL_ENONFINITE = -5,  /* NaN or Inf in a state                             */
+    QL_EPOSITIVITY = -6, /* non-positive density/pressure or q4 >= 0          */
+    QL_EDIVERGED = -7,   /* reserved: residual blow-up                        */
+    QL_ESTATE = -8       /* call out of order                                 */
+};
+
+/* point kinds */
+enum { QL_KIND_INTERIOR = 0, QL_KIND_WALL = 1, QL_KIND_OUTER = 2 };
+
+/* Split-stencil membership bits of one neighbour entry (sec. 2 eq. (14)),
+ * in the point's frame: s along t = (n_y, -n_x), n along the point's unit
+ * normal.  S_PLUS: ds < 0, S_MINUS: ds > 0, N_PLUS: dn < 0, N_MINUS: dn > 0;
+ * an entry with |ds| <= 1e-12 |d| (resp. dn) is in neither s (n) half. */
+enum { QL_SPLIT_S_PLUS = 1, QL_SPLIT_S_MINUS = 2, QL_SPLIT_N_PLUS = 4, QL_SPLIT_N_MINUS = 8 };
+
+typedef struct {
+    double gamma;     /* ratio of specific heats (1.4)                          */
+    double mach;      /* freestream Mach number (rho_inf = 1, c_inf = 1)        */
+    double alpha_deg; /* angle of attack, degrees                               */
+    double cfl;       /* local time step dt = cfl * min|P_i - P| / (|u| + c)     */
+    int32_t n_inner;  /* inner iterations of the q-derivatives (3), >= 0        */
+    int32_t limiter;  /* 0 none, 1 Venkatakrishnan                              */
+    double venkat_k;  /* limiter constant K, eps^2 = (K |P_i - P|)^3            */
+    int32_t precision;/* 0 FP64 throughout                                      */
+    int32_t reorder;  /* read at upload: 0 caller order, 1 Hilbert curve        */
+} ql_params;
+
+/* Fill *p with the defaults: gamma 1.4, M 0.63, alpha 2, CFL 0.2, 3 inner
+ * iterations, limiter off (K = 5), FP64, Hilbert reorder. */
+void ql_default_params(ql_params *p);
+
+/* Create a solver on HIP device `device`.  `hip_stream` is a hipStream_t
+ * (for example torch.cuda.current_stream().cuda_stream) on which every
+ * kernel and copy of this solver is enqueued; NULL makes the library create
+ * its own stream.  *out receives the handle (NULL on failure).
+ * Errors: QL_EINVAL (out NULL), QL_EDEVICE. */
+int ql_create(ql_solver **out, int32_t device, void *hip_stream);
+
+/* Free every buffer of the solver (NULL is a no-op). */
+int ql_destroy(ql_solver *s);
+
+/* Upload a point cloud (sec. 3: the input data structure copied to the
+ * device once).  Host arrays, caller order:
+ *   x, y, nx, ny : double[n]   positions and unit normals (frame of the
+ *                              split stencils; at wall points the normal
+ *                              points into the fluid)
+ *   kind         : uint8[n]    QL_KIND_*
+ *   nbr_ptr      : int32[n+1]  CSR row pointers, nbr_ptr[0] = 0
+ *   nbr_idx      : int32[nnz]  neighbours of each point (no self, in range);
+ *                              their order is kept for every sum
+ *   nbr_flag     : uint8[nnz]  split membership (QL_SPLIT_* bits) or NULL to
+ *                              let the library classify the entries.
+ * The library validates the CSR, reorders points (params.reorder), and on
+ * the device classifies entries, precomputes least-squares factors and
+ * checks that every matrix the scheme inverts is non-singular: the full
+ * stencil of every point and each split stencil entering the residual
+ * (interior: all four; wall: s+, s-, n-), each needing >= 2 points and
+ * det > 1e-12 (sum ds^2 + sum dn^2)^2.
+ * Errors: QL_EINVAL (malformed input), QL_ESINGULAR (message names the
+ * point), QL_ENOMEM, QL_EDEVICE.  Any previous cloud and state are dropped. */
+int ql_upload_cloud(ql_solver *s, int64_t n, const double *x, const double *y,
+                    const double *nx, const double *ny, const uint8_t *kind,
+                    const int32_t *nbr_ptr, const int32_t *nbr_idx,
+                    const uint8_t *nbr_flag);
+
+/* Set flow and solver parameters (copied).  Errors: QL_EINVAL. */
+int ql_set_params(ql_solver *s, const ql_params *p);
+
+/* Set every point to the freestream (rho 1, p 1/gamma, u = M (cos a, sin a))
+ * and project the wall points' momentum onto the wall tangent.
+ * Errors: QL_ESTATE (no cloud), QL_EDEVICE. */
+int ql_init_freestream(ql_solver *s);
+
+/* Set the conserved state from U[4][n] (caller order; mem 0 host, 1 device).
+ * project_wall != 0 applies the wall projection m <- m - (m.n) n.
+ * Errors: QL_ESTATE, QL_ENONFINITE / QL_EPOSITIVITY (message names the
+ * first point), QL_EDEVICE. */
+int ql_set_state(ql_solver *s, const double *U, int32_t mem, int32_t project_wall);
+
+/* Run n_iter pseudo-time iterations (sec. 3 Algorithm 1): per iteration the
+ * local time step, four stages of four-stage third-order SSP Runge-Kutta,
+ * and the residual norm of the first stage's residual.  res_hist (host,
+ * nullable) receives [n_iter][4] residual norms (root mean square over the
+ * interior and wall points of each component).  Enqueues on the solver's
+ * stream and synchronises once at the end.
+ * Errors: QL_ESTATE, QL_EPOSITIVITY / QL_ENONFINITE (first point of the
+ * first failing launch; the state is then undefined), QL_EDEVICE. */
+int ql_step(ql_solver *s, int32_t n_iter, double *res_hist);
+
+/* Residual norms of the last iteration ql_step ran.  Errors: QL_ESTATE. */
+int ql_residual_norm(const ql_solver *s, double out[4]);
+
+/* Copy the conserved state to U[4][n] in caller order (mem 0 host, 1
+ * device).  Synchronises.  Errors: QL_ESTATE, QL_EDEVICE. */
+int ql_fetch_state(ql_solver *s, double *U, int32_t mem);
+
+/* Lift and drag coefficients of the current state from the wall pressure:
+ * F = -sum (p - p_inf) n ds over wall points, where the wall points in the
+ * caller's order form the closed surface polygon and
+ * ds = (|S_next - S| + |S - S_prev|)/2; the upper (y > 0), lower (y < 0)
+ * and on-axis parts are summed separately, then added.
+ * Cl = F.(-sin a, cos a)/q_inf, Cd = F.(cos a, sin a)/q_inf.
+ * Errors: QL_ESTATE, QL_EINVAL (fewer than 3 wall points), QL_EDEVICE. */
+int ql_forces(ql_solver *s, double *cl, double *cd);
+
+/* Message of the last failing call on this solver ("" if none). */
+const char *ql_last_error(const ql_solver *s);
+
+/* --- inspection and timing (tests, benchmarks) ------------------------- */
+
+/* One evaluation of the stage operator at the current state, without
+ * updating it: q, the q-derivatives after n_inner inner iterations, the
+ * limiter bounds, the residual R and the time step.  Fetch them with
+ * ql_debug_fetch.  Errors as ql_step. */
+int ql_evaluate(ql_solver *s);
+
+/* Copy an inspection array to host memory `out` in caller order:
+ *   0 q [4][n]       1 g [8][n] (q_x rows 0..3, q_y rows 4..7)
+ *   2 R [4][n]       3 dt [n]
+ *   4 qmax [4][n]    5 qmin [4][n]
+ * After ql_evaluate all six hold that evaluation; after ql_step, 0 and 3
+ * hold the current state's q and time step.  Errors: QL_EINVAL, QL_ESTATE. */
+int ql_debug_fetch(ql_solver *s, int32_t what, double *out);
+
+/* Copy the split-membership flags to uint8 out[nnz] in the caller's CSR
+ * entry order.  Errors: QL_ESTATE. */
+int ql_debug_flags(ql_solver *s, uint8_t *out);
+
+/* Number of points and neighbour entries of the uploaded cloud. */
+int ql_cloud_size(const ql_solver *s, int64_t *n, int64_t *nnz);
+
+/* Kernel timing: when enabled, ql_step brackets every launch with HIP
+ * events on the solver's stream.  ql_kernel_time returns, for kernel kind
+ * `which` (0 gradient first pass, 1 gradient inner iteration, 2 flux
+ * residual + update, 3 residual norm), the summed duration in ms and the
+ * launch count since timing was last enabled.  Errors: QL_EINVAL. */
+int ql_set_timing(ql_solver *s, int32_t enable);
+int ql_kernel_time(const ql_solver *s, int32_t which, double *total_ms, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QLSKUM_H */

@@ -20,12 +20,22 @@ OK, EINVAL, ESINGULAR, ENOMEM, ENONFINITE, EPOSITIVITY = 0, -1, -2, -3, -5, -6
 S_PLUS, S_MINUS, N_PLUS, N_MINUS = 1, 2, 4, 8
 
 
+FMA_LIB = os.path.join(_HERE, "liboracle_fma.so")
+
+
 def build(cflags=("-O2", "-ffp-contract=off"), out=_LIB):
     """Compile the oracle with gcc (no FMA contraction) into a shared library."""
     cmd = ["gcc", "-std=c99", *cflags, "-fPIC", "-shared", "-o", out + ".tmp", _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(out + ".tmp", out)
     return out
+
+
+def build_fma():
+    """The same source with FMA contraction: a second, equally valid FP64
+    evaluation whose distance from the first measures the rounding noise
+    floor of a problem (used to set tolerances where conditioning is poor)."""
+    return build(cflags=("-O2", "-mfma", "-ffp-contract=fast"), out=FMA_LIB)
 
 
 class OracleError(RuntimeError):
@@ -53,9 +63,12 @@ def load(path=_LIB):
     if path in _lib_cache:
         return _lib_cache[path]
     if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
-        if path != _LIB:
+        if path == _LIB:
+            build()
+        elif path == FMA_LIB:
+            build_fma()
+        else:
             raise FileNotFoundError(path)
-        build()
     lib = C.CDLL(path)
     vp, i64, i32, d = C.c_void_p, C.c_int64, C.c_int32, C.c_double
     P = C.POINTER

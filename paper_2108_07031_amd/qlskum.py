@@ -1,0 +1,283 @@
+"""Thin ctypes binding of libqlskum.so (include/qlskum.h).
+
+Every function keeps the C name and only marshals arguments: numpy arrays
+for host memory, torch CUDA tensors (or raw integer device pointers) for
+device memory, torch's current stream for ordering.  All computation runs
+in the library's HIP kernels; there is no fallback: if the library is not
+built, importing this module raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqlskum.so")
+
+QL_OK, QL_EINVAL, QL_ESINGULAR, QL_ENOMEM, QL_EDEVICE = 0, -1, -2, -3, -4
+QL_ENONFINITE, QL_EPOSITIVITY, QL_EDIVERGED, QL_ESTATE = -5, -6, -7, -8
+QL_KIND_INTERIOR, QL_KIND_WALL, QL_KIND_OUTER = 0, 1, 2
+QL_SPLIT_S_PLUS, QL_SPLIT_S_MINUS, QL_SPLIT_N_PLUS, QL_SPLIT_N_MINUS = 1, 2, 4, 8
+
+# every entry point the public header declares
+EXPORTS = ("ql_default_params", "ql_create", "ql_destroy", "ql_upload_cloud", "ql_set_params",
+           "ql_init_freestream", "ql_set_state", "ql_step", "ql_residual_norm",
+           "ql_fetch_state", "ql_forces", "ql_last_error", "ql_evaluate", "ql_debug_fetch",
+           "ql_debug_flags", "ql_cloud_size", "ql_set_timing", "ql_kernel_time")
+
+
+class ql_params(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("mach", C.c_double), ("alpha_deg", C.c_double),
+                ("cfl", C.c_double), ("n_inner", C.c_int32), ("limiter", C.c_int32),
+                ("venkat_k", C.c_double), ("precision", C.c_int32), ("reorder", C.c_int32)]
+
+
+class QLError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"qlskum error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2108_07031_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    P = C.POINTER
+    lib.ql_default_params.argtypes = [P(ql_params)]
+    lib.ql_default_params.restype = None
+    lib.ql_create.argtypes = [P(vp), i32, vp]
+    lib.ql_destroy.argtypes = [vp]
+    lib.ql_upload_cloud.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.ql_set_params.argtypes = [vp, P(ql_params)]
+    lib.ql_init_freestream.argtypes = [vp]
+    lib.ql_set_state.argtypes = [vp, vp, i32, i32]
+    lib.ql_step.argtypes = [vp, i32, vp]
+    lib.ql_residual_norm.argtypes = [vp, vp]
+    lib.ql_fetch_state.argtypes = [vp, vp, i32]
+    lib.ql_forces.argtypes = [vp, P(d), P(d)]
+    lib.ql_last_error.argtypes = [vp]
+    lib.ql_last_error.restype = C.c_char_p
+    lib.ql_evaluate.argtypes = [vp]
+    lib.ql_debug_fetch.argtypes = [vp, i32, vp]
+    lib.ql_debug_flags.argtypes = [vp, vp]
+    lib.ql_cloud_size.argtypes = [vp, P(i64), P(i64)]
+    lib.ql_set_timing.argtypes = [vp, i32]
+    lib.ql_kernel_time.argtypes = [vp, i32, P(d), P(i64)]
+    for name in EXPORTS:
+        if name not in ("ql_default_params", "ql_last_error"):
+            getattr(lib, name).restype = C.c_int
+    return lib
+
+
+lib = _load()
+
+
+def _check(s, rc):
+    if rc != QL_OK:
+        msg = lib.ql_last_error(s).decode() if s else ""
+        raise QLError(rc, msg)
+    return rc
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data
+
+
+def _dev_ptr(t):
+    """Device pointer of a torch CUDA tensor (contiguous) or an int."""
+    if isinstance(t, int):
+        return t
+    if not t.is_contiguous():
+        raise ValueError("device tensor must be contiguous")
+    return t.data_ptr()
+
+
+def ql_default_params():
+    p = ql_params()
+    lib.ql_default_params(C.byref(p))
+    return p
+
+
+def ql_create(device=0, stream=None):
+    """stream: hipStream_t as int, a torch stream, or None for torch's
+    current stream on `device` (the library creates its own if torch has
+    no GPU)."""
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream(device).cuda_stream
+    elif not isinstance(stream, int):
+        stream = stream.cuda_stream
+    h = C.c_void_p()
+    rc = lib.ql_create(C.byref(h), int(device), C.c_void_p(stream) if stream else None)
+    if rc != QL_OK:
+        raise QLError(rc, "ql_create failed")
+    return h
+
+
+def ql_destroy(s):
+    return lib.ql_destroy(s)
+
+
+def ql_upload_cloud(s, x, y, nx, ny, kind, nbr_ptr, nbr_idx, nbr_flag=None):
+    keep = [_host(x, np.float64), _host(y, np.float64), _host(nx, np.float64),
+            _host(ny, np.float64), _host(kind, np.uint8), _host(nbr_ptr, np.int32),
+            _host(nbr_idx, np.int32)]
+    fl = _host(nbr_flag, np.uint8) if nbr_flag is not None else (None, None)
+    n = keep[0][0].shape[0]
+    return _check(s, lib.ql_upload_cloud(s, n, *(k[1] for k in keep), fl[1]))
+
+
+def ql_set_params(s, p):
+    return _check(s, lib.ql_set_params(s, C.byref(p)))
+
+
+def ql_init_freestream(s):
+    return _check(s, lib.ql_init_freestream(s))
+
+
+def ql_set_state(s, U, project_wall=False):
+    """U: numpy (4, n) on the host, or a torch CUDA tensor (4, n) on the
+    solver's device."""
+    if isinstance(U, np.ndarray):
+        a, ptr = _host(U, np.float64)
+        return _check(s, lib.ql_set_state(s, ptr, 0, int(bool(project_wall))))
+    return _check(s, lib.ql_set_state(s, _dev_ptr(U), 1, int(bool(project_wall))))
+
+
+def ql_step(s, n_iter, want_history=True):
+    """Returns the (n_iter, 4) residual history (or None)."""
+    hist = np.zeros((max(n_iter, 1), 4)) if want_history else None
+    _check(s, lib.ql_step(s, int(n_iter), hist.ctypes.data if want_history else None))
+    return hist[:n_iter] if want_history else None
+
+
+def ql_residual_norm(s):
+    out = np.zeros(4)
+    _check(s, lib.ql_residual_norm(s, out.ctypes.data))
+    return out
+
+
+def ql_cloud_size(s):
+    n, nnz = C.c_int64(), C.c_int64()
+    _check(s, lib.ql_cloud_size(s, C.byref(n), C.byref(nnz)))
+    return n.value, nnz.value
+
+
+def ql_fetch_state(s, out=None):
+    """Into a new host array (4, n), or into `out` (numpy or torch CUDA)."""
+    n, _ = ql_cloud_size(s)
+    if out is None:
+        out = np.empty((4, n))
+    if isinstance(out, np.ndarray):
+        if out.dtype != np.float64 or not out.flags.c_contiguous or out.shape != (4, n):
+            raise ValueError("out must be C-contiguous float64 (4, n)")
+        _check(s, lib.ql_fetch_state(s, out.ctypes.data, 0))
+    else:
+        _check(s, lib.ql_fetch_state(s, _dev_ptr(out), 1))
+    return out
+
+
+def ql_forces(s):
+    cl, cd = C.c_double(), C.c_double()
+    _check(s, lib.ql_forces(s, C.byref(cl), C.byref(cd)))
+    return cl.value, cd.value
+
+
+def ql_last_error(s):
+    return lib.ql_last_error(s).decode()
+
+
+def ql_evaluate(s):
+    return _check(s, lib.ql_evaluate(s))
+
+
+_DEBUG_ROWS = {0: 4, 1: 8, 2: 4, 3: 1, 4: 4, 5: 4}
+
+
+def ql_debug_fetch(s, what):
+    n, _ = ql_cloud_size(s)
+    rows = _DEBUG_ROWS[what]
+    out = np.empty((rows, n)) if rows > 1 else np.empty(n)
+    _check(s, lib.ql_debug_fetch(s, int(what), out.ctypes.data))
+    return out
+
+
+def ql_debug_flags(s):
+    _, nnz = ql_cloud_size(s)
+    out = np.empty(nnz, np.uint8)
+    _check(s, lib.ql_debug_flags(s, out.ctypes.data))
+    return out
+
+
+def ql_set_timing(s, enable):
+    return _check(s, lib.ql_set_timing(s, int(bool(enable))))
+
+
+def ql_kernel_time(s, which):
+    ms, cnt = C.c_double(), C.c_int64()
+    _check(s, lib.ql_kernel_time(s, int(which), C.byref(ms), C.byref(cnt)))
+    return ms.value, cnt.value
+
+
+def params(**kw):
+    """ql_params with defaults overridden by keyword."""
+    p = ql_default_params()
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+class Solver:
+    """Convenience owner of one solver handle (same calls, bound)."""
+
+    def __init__(self, cloud=None, device=0, stream=None, **prm):
+        self.h = ql_create(device, stream)
+        if prm:
+            ql_set_params(self.h, params(**prm))
+        if cloud is not None:
+            self.upload(cloud)
+
+    def upload(self, cloud, nbr_flag=None):
+        ql_upload_cloud(self.h, cloud.x, cloud.y, cloud.nx, cloud.ny, cloud.kind,
+                        cloud.nbr_ptr, cloud.nbr_idx, nbr_flag)
+
+    def set_params(self, **prm):
+        ql_set_params(self.h, params(**prm))
+
+    def init_freestream(self):
+        ql_init_freestream(self.h)
+
+    def set_state(self, U, project_wall=False):
+        ql_set_state(self.h, U, project_wall)
+
+    def step(self, n_iter, want_history=True):
+        return ql_step(self.h, n_iter, want_history)
+
+    def fetch_state(self, out=None):
+        return ql_fetch_state(self.h, out)
+
+    def forces(self):
+        return ql_forces(self.h)
+
+    def evaluate(self):
+        ql_evaluate(self.h)
+        return {name: ql_debug_fetch(self.h, w) for w, name in
+                enumerate(("q", "g", "R", "dt", "qmax", "qmin"))}
+
+    def flags(self):
+        return ql_debug_flags(self.h)
+
+    def close(self):
+        if self.h:
+            ql_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
