@@ -268,13 +268,15 @@ def _half_plane_quality(x, y, nx, ny, kind, ptr, idx):
     return cnt, qual, need
 
 
-def enrich_half_planes(x, y, nx, ny, kind, ptr, idx, cap, min_quality=1e-9, pool=1024):
-    """Add neighbours where a needed split half plane is degenerate (fewer
-    than 2 points or a nearly collinear set): the nearest points of that
-    half plane not yet in the stencil, one at a time, until its normalised
-    determinant exceeds `min_quality` (at most `cap` neighbours)."""
+def enrich_half_planes(x, y, nx, ny, kind, ptr, idx, cap, min_quality=1e-4, min_count=3,
+                       pool=1024):
+    """Add neighbours where a needed split half plane is poorly conditioned
+    (fewer than `min_count` points or a normalised determinant below
+    `min_quality`, e.g. the on-axis points behind a sharp trailing edge): the
+    nearest points of that half plane not yet in the stencil that improve
+    it, one at a time, until both bounds hold (at most `cap` neighbours)."""
     cnt, qual, need = _half_plane_quality(x, y, nx, ny, kind, ptr, idx)
-    bad = np.flatnonzero(np.any(need & ((cnt < 2) | (qual <= min_quality)), axis=0))
+    bad = np.flatnonzero(np.any(need & ((cnt < min_count) | (qual <= min_quality)), axis=0))
     if bad.size == 0:
         return ptr, idx
     tree = cKDTree(np.stack([x, y], axis=1))
@@ -300,25 +302,25 @@ def enrich_half_planes(x, y, nx, ny, kind, ptr, idx, cap, min_quality=1e-9, pool
                 continue
             sel = [v for v in (local(p, i) for i in cur) if _in_half(v, h)]
             qcur = quality(sel)
-            for c_ in cand[row]:
-                if qcur > min_quality:
-                    break
-                c_ = int(c_)
-                if c_ == p or c_ in cur:
-                    continue
-                v = local(p, c_)
-                if not _in_half(v, h):
-                    continue
-                qnew = quality(sel + [v])
-                if qnew <= qcur:
-                    continue  # collinear with what is there: no help
-                if len(cur) >= cap:
+            while qcur <= min_quality or len(sel) < min_count:
+                # the nearest few candidates of this half plane; take the one
+                # that conditions it best
+                opts = []
+                for c_ in cand[row]:
+                    c_ = int(c_)
+                    if c_ == p or c_ in cur:
+                        continue
+                    v = local(p, c_)
+                    if _in_half(v, h):
+                        opts.append((c_, v))
+                        if len(opts) == 8:
+                            break
+                if not opts or len(cur) >= cap:
                     raise ValueError(f"cannot repair split stencil {h} of point {p}")
-                cur.append(c_)
-                sel.append(v)
-                qcur = qnew
-            if qcur <= min_quality:
-                raise ValueError(f"cannot repair split stencil {h} of point {p}")
+                best = max(opts, key=lambda o: quality(sel + [o[1]]))
+                cur.append(best[0])
+                sel.append(best[1])
+                qcur = quality(sel)
     counts = np.diff(ptr).astype(np.int64)
     for p in bad:
         counts[p] = len(lists[int(p)])
