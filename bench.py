@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 NS, NR = 1250, 2000
 FLOW = dict(mach=0.85, alpha_deg=1.0, limiter=1, venkat_k=5.0, cfl=0.2, n_inner=3)
 FP64_VALU_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak
+PREC_NAME = {0: "fp64", 1: "mixed"}
 
 # Algorithmic FP64 operations of the flux-residual kernel, per neighbour
 # entry that enters at least one split stencil, and per split stencil it
@@ -76,6 +77,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=("both", "fp64", "mixed"), default="both")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -93,60 +95,65 @@ def main():
     torch.cuda.init()
     stream = torch.cuda.Stream()  # default priority
     torch.cuda.set_stream(stream)
-    s = ql.Solver(cloud, stream=stream, **FLOW)
-    flags = s.flags()
-    flops = flux_flops_per_launch(flags, cloud.kind, cloud.nbr_ptr, FLOW["limiter"])
-    s.init_freestream()
-    log("warmup")
-    s.step(args.warmup, want_history=False)
 
-    ql.ql_set_timing(s.h, 1)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    log(f"timed: {args.steps} iterations")
-    wall0 = time.perf_counter()
-    ev0.record(stream)
-    hist = s.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    gpu_ms = ev0.elapsed_time(ev1)
-    ktime = {k: ql.ql_kernel_time(s.h, k) for k in range(4)}
-    ql.ql_set_timing(s.h, 0)
-    log(f"wall {wall:.3f} s, events {gpu_ms / 1e3:.3f} s, residual {hist[0, 0]:.3e} -> "
-        f"{hist[-1, 0]:.3e}")
-    for k, name in enumerate(("grad0", "gradk", "flux", "resnorm")):
-        ms, cnt = ktime[k]
-        log(f"  {name}: {cnt} launches, avg {ms / max(cnt, 1) * 1e3:.1f} us, "
-            f"share {ms / gpu_ms * 100:.1f}%")
-    cl, cd = s.forces()
-    s.close()
+    def timed_run(precision):
+        s = ql.Solver(cloud, stream=stream, precision=precision, **FLOW)
+        flags = s.flags()
+        s.init_freestream()
+        log(f"[{PREC_NAME[precision]}] warmup {args.warmup}")
+        s.step(args.warmup, want_history=False)
+        ql.ql_set_timing(s.h, 1)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        log(f"[{PREC_NAME[precision]}] timed: {args.steps} iterations")
+        wall0 = time.perf_counter()
+        ev0.record(stream)
+        hist = s.step(args.steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        gpu_ms = ev0.elapsed_time(ev1)
+        ktime = {k: ql.ql_kernel_time(s.h, k) for k in range(4)}
+        ql.ql_set_timing(s.h, 0)
+        log(f"[{PREC_NAME[precision]}] wall {wall:.3f} s, events {gpu_ms / 1e3:.3f} s, "
+            f"residual {hist[0, 0]:.3e} -> {hist[-1, 0]:.3e}")
+        for k, name in enumerate(("grad0", "gradk", "flux", "resnorm")):
+            ms, cnt = ktime[k]
+            log(f"  {name}: {cnt} launches, avg {ms / max(cnt, 1) * 1e3:.1f} us, "
+                f"share {ms / gpu_ms * 100:.1f}%")
+        cl, cd = s.forces()
+        s.close()
+        elapsed = max(wall, gpu_ms / 1e3)
+        return dict(flags=flags, elapsed=elapsed, ktime=ktime, hist=hist, cl=cl, cd=cd,
+                    value=cloud.n * args.steps / elapsed / 1e6)
 
-    elapsed = max(wall, gpu_ms / 1e3)
-    value = cloud.n * args.steps / elapsed / 1e6
-    flux_ms, flux_cnt = ktime[2]
+    runs = {p: timed_run(p) for p in ((0, 1) if args.precision == "both" else
+                                      (0,) if args.precision == "fp64" else (1,))}
+    head = runs[0] if 0 in runs else runs[1]
+    flops = flux_flops_per_launch(head["flags"], cloud.kind, cloud.nbr_ptr, FLOW["limiter"])
+    flux_ms, flux_cnt = head["ktime"][2]
     flux_avg_s = flux_ms / max(flux_cnt, 1) / 1e3
     achieved = flops / flux_avg_s / 1e12
     out = {
         "metric": "Mpoint-iter/s at 2.5M pts, FP64 vs mixed; time to 1e-6 residual, warm vs cold",
-        "value": value,
+        "value": head["value"],
         "unit": "Mpoint-iter/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "ms_per_step": head["elapsed"] * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if 0 in runs else "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": "q-LSKUM FP64, NACA 0012 O-cloud 1250x2000 (2.5M pts), jitter 0.1 "
+            "workload": "q-LSKUM, NACA 0012 O-cloud 1250x2000 (2.5M pts), jitter 0.1 "
                         "seed 2108, Hilbert order, M 0.85, alpha 1, Venkatakrishnan K 5, "
                         "CFL 0.2, 3 inner iterations",
             "n_points": cloud.n,
             "nnz": cloud.nnz,
-            "precision": "fp64",
+            "precision": "fp64" if 0 in runs else "mixed",
         },
         "roofline": {
             "kernel": "k_flux (flux residual + RK stage)",
@@ -159,9 +166,14 @@ def main():
             "flops_per_launch": flops,
             "avg_launch_us": flux_avg_s * 1e6,
         },
-        "residual_first_last": [float(hist[0, 0]), float(hist[-1, 0])],
-        "cl_cd": [cl, cd],
+        "residual_first_last": [float(head["hist"][0, 0]), float(head["hist"][-1, 0])],
+        "cl_cd": [head["cl"], head["cd"]],
     }
+    if 0 in runs and 1 in runs:
+        out["mixed"] = {"value": runs[1]["value"], "unit": "Mpoint-iter/s",
+                        "ms_per_step": runs[1]["elapsed"] * 1e3 / args.steps,
+                        "over_fp64": runs[1]["value"] / runs[0]["value"],
+                        "dtype": "f32 flux body, f64 sums and update"}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one stage of the full cloud)")
         out["cpu_baseline"] = cpu_baseline(cloud)

@@ -70,7 +70,9 @@ typedef struct {
     int32_t n_inner;  /* inner iterations of the q-derivatives (3), >= 0        */
     int32_t limiter;  /* 0 none, 1 Venkatakrishnan                              */
     double venkat_k;  /* limiter constant K, eps^2 = (K |P_i - P|)^3            */
-    int32_t precision;/* 0 FP64 throughout                                      */
+    int32_t precision;/* 0 FP64 throughout; 1 mixed: reconstruction, limiter
+                         and split fluxes in FP32, least-squares weights,
+                         residual sums and the state update in FP64           */
     int32_t reorder;  /* read at upload: 0 caller order, 1 Hilbert curve        */
 } ql_params;
 

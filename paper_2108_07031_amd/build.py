@@ -10,7 +10,10 @@ SOURCES = ["qlskum_kernels.hip", "qlskum_runtime.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed FP32 instructions are kept out of every code object
+# FP32 divide and square root use the hardware approximations (the mixed
+# precision path is FP32 only where the accuracy budget allows it)
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
+         "-fno-hip-fp32-correctly-rounded-divide-sqrt",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 

@@ -67,6 +67,10 @@ __device__ __forceinline__ void store8(double2 *a, int p, const double v[8]) {
     a[4 * p + 3] = make_double2(v[6], v[7]);
 }
 
+__device__ __forceinline__ float4 to_f4(const double v[4]) {
+    return make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+}
+
 // U -> q (eq. (26)); returns an ErrCode.
 __device__ __forceinline__ int cons_to_q(const double U[4], const FlowParams &fp, double q[4]) {
     if (!isfinite(U[0]) || !isfinite(U[1]) || !isfinite(U[2]) || !isfinite(U[3]))
@@ -257,7 +261,8 @@ hipError_t launch_unpermute_state(hipStream_t st, int n, const double *U, const 
 __global__ void __launch_bounds__(kBlock) k_prep(DevCloud cl, FlowParams fp,
                                                  const double *__restrict__ U,
                                                  double *__restrict__ Un, double2 *__restrict__ q,
-                                                 double *__restrict__ dt, int *err) {
+                                                 double *__restrict__ dt, float4 *__restrict__ q32,
+                                                 int *err) {
     const int n = cl.n;
     const int p = point_id();
     if (p >= n) return;
@@ -271,15 +276,16 @@ __global__ void __launch_bounds__(kBlock) k_prep(DevCloud cl, FlowParams fp,
         qq[3] = -1.0;
     }
     store4(q, p, qq);
+    if (q32) q32[p] = to_f4(qq);
 #pragma unroll
     for (int c = 0; c < 4; ++c) Un[(size_t)c * n + p] = v[c];
     dt[p] = local_dt(v, cl.dmin[p], fp);
 }
 
 hipError_t launch_prep(hipStream_t st, const DevCloud &c, const FlowParams &fp, const double *U,
-                       double *Un, double2 *q, double *dt, int *err) {
+                       double *Un, double2 *q, double *dt, float4 *q32, int *err) {
     hipLaunchKernelGGL(k_prep, dim3(num_blocks(c.n)), dim3(kBlock), 0, st, c, fp, U, Un, q, dt,
-                       err);
+                       q32, err);
     return hipGetLastError();
 }
 
@@ -290,7 +296,8 @@ hipError_t launch_prep(hipStream_t st, const DevCloud &c, const FlowParams &fp, 
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_grad0(DevCloud cl, const double2 *__restrict__ q,
                                                   double2 *__restrict__ g,
-                                                  double2 *__restrict__ qmm, int want_bounds) {
+                                                  double2 *__restrict__ qmm, int want_bounds,
+                                                  Shadow sh) {
     const int p = point_id();
     if (p >= cl.n) return;
     const double2 P = cl.xy[p];
@@ -326,16 +333,24 @@ __global__ void __launch_bounds__(kBlock) k_grad0(DevCloud cl, const double2 *__
         gv[4 + r] = (a * sy[r] - b * sx[r]) / D;
     }
     store8(g, p, gv);
+    if (sh.g32) {
+        sh.g32[2 * p] = to_f4(gv);
+        sh.g32[2 * p + 1] = to_f4(gv + 4);
+    }
     if (want_bounds) {
         double bv[8] = {mx[0], mx[1], mx[2], mx[3], mn[0], mn[1], mn[2], mn[3]};
         store8(qmm, p, bv);
+        if (sh.qmm32) {
+            sh.qmm32[2 * p] = to_f4(bv);
+            sh.qmm32[2 * p + 1] = to_f4(bv + 4);
+        }
     }
 }
 
 hipError_t launch_grad0(hipStream_t st, const DevCloud &c, const double2 *q, double2 *g,
-                        double2 *qmm, int want_bounds) {
+                        double2 *qmm, int want_bounds, Shadow sh) {
     hipLaunchKernelGGL(k_grad0, dim3(num_blocks(c.n)), dim3(kBlock), 0, st, c, q, g, qmm,
-                       want_bounds);
+                       want_bounds, sh);
     return hipGetLastError();
 }
 
@@ -346,7 +361,8 @@ hipError_t launch_grad0(hipStream_t st, const DevCloud &c, const double2 *q, dou
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_gradk(DevCloud cl, const double2 *__restrict__ q,
                                                   const double2 *__restrict__ gprev,
-                                                  double2 *__restrict__ gnext) {
+                                                  double2 *__restrict__ gnext,
+                                                  float4 *__restrict__ g32) {
     const int p = point_id();
     if (p >= cl.n) return;
     const double2 P = cl.xy[p];
@@ -382,11 +398,215 @@ __global__ void __launch_bounds__(kBlock) k_gradk(DevCloud cl, const double2 *__
         gv[4 + r] = (a * sy[r] - b * sx[r]) / D;
     }
     store8(gnext, p, gv);
+    if (g32) {
+        g32[2 * p] = to_f4(gv);
+        g32[2 * p + 1] = to_f4(gv + 4);
+    }
 }
 
 hipError_t launch_gradk(hipStream_t st, const DevCloud &c, const double2 *q, const double2 *gprev,
-                        double2 *gnext) {
-    hipLaunchKernelGGL(k_gradk, dim3(num_blocks(c.n)), dim3(kBlock), 0, st, c, q, gprev, gnext);
+                        double2 *gnext, float4 *g32) {
+    hipLaunchKernelGGL(k_gradk, dim3(num_blocks(c.n)), dim3(kBlock), 0, st, c, q, gprev, gnext,
+                       g32);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// LDS-tiled q-derivatives.  A workgroup owns a tile of kBlock consecutive
+// points (a compact patch in Hilbert order); it first copies the records of
+// its points and of their neighbours outside the tile (the halo) into LDS,
+// then every lane walks its neighbour list through 16-bit slot indices.
+// Each record is read from memory once per tile instead of once per use.
+// ---------------------------------------------------------------------------
+// Tiles whose image exceeds the budget read their neighbours straight from
+// memory (a branch that is uniform across the workgroup).
+constexpr int kLdsBudget = 64 * 1024;  // bytes of LDS per workgroup at most
+constexpr int kCap0 = kLdsBudget / 48;  // slots of the first-pass image
+constexpr int kCapK = kLdsBudget / 80;  // slots of the inner-iteration image
+
+bool lds_fits_grad0(const DevCloud &c) { return c.max_slots < (1 << 30); }
+bool lds_fits_gradk(const DevCloud &c) { return c.max_slots < (1 << 30); }
+
+// first pass: slot record = (q0,q1) (q2,q3) (x,y)
+__global__ void __launch_bounds__(kBlock) k_grad0_lds(DevCloud cl, const double2 *__restrict__ q,
+                                                      double2 *__restrict__ g,
+                                                      double2 *__restrict__ qmm,
+                                                      int want_bounds, Shadow sh) {
+    extern __shared__ double2 lds[];
+    const int n = cl.n;
+    const int t = logical_block();
+    const int base = t * kBlock;
+    const int h0 = cl.halo_ptr[t], nh = cl.halo_ptr[t + 1] - h0;
+    const int nown = min(kBlock, n - base);
+    const bool in_lds = kBlock + nh <= kCap0;
+    if (in_lds) {
+        for (int s = threadIdx.x; s < kBlock + nh; s += kBlock) {
+            int pt;
+            if (s < kBlock) {
+                if (s >= nown) continue;
+                pt = base + s;
+            } else {
+                pt = cl.halo_idx[h0 + s - kBlock];
+            }
+            lds[3 * s] = q[2 * pt];
+            lds[3 * s + 1] = q[2 * pt + 1];
+            lds[3 * s + 2] = cl.xy[pt];
+        }
+    }
+    __syncthreads();
+    const int j = threadIdx.x;
+    if (j >= nown) return;
+    const int p = base + j;
+    const double2 q01 = q[2 * p], q23 = q[2 * p + 1], P = cl.xy[p];
+    const double qp[4] = {q01.x, q01.y, q23.x, q23.y};
+    double a = 0.0, b = 0.0, c = 0.0;
+    double sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
+    double mx[4] = {qp[0], qp[1], qp[2], qp[3]}, mn[4] = {qp[0], qp[1], qp[2], qp[3]};
+    const int k1 = cl.ptr[p + 1];
+    for (int k = cl.ptr[p]; k < k1; ++k) {
+        double2 a01, a23, Q;
+        if (in_lds) {
+            const int li = cl.lidx[k];
+            a01 = lds[3 * li];
+            a23 = lds[3 * li + 1];
+            Q = lds[3 * li + 2];
+        } else {
+            const int i = cl.idx[k];
+            a01 = q[2 * i];
+            a23 = q[2 * i + 1];
+            Q = cl.xy[i];
+        }
+        const double qi[4] = {a01.x, a01.y, a23.x, a23.y};
+        const double dx = Q.x - P.x, dy = Q.y - P.y;
+        a += dx * dx;
+        b += dx * dy;
+        c += dy * dy;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double dq = qi[r] - qp[r];
+            sx[r] += dx * dq;
+            sy[r] += dy * dq;
+            mx[r] = fmax(mx[r], qi[r]);
+            mn[r] = fmin(mn[r], qi[r]);
+        }
+    }
+    const double D = a * c - b * b;
+    double gv[8];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        gv[r] = (c * sx[r] - b * sy[r]) / D;
+        gv[4 + r] = (a * sy[r] - b * sx[r]) / D;
+    }
+    store8(g, p, gv);
+    if (sh.g32) {
+        sh.g32[2 * p] = to_f4(gv);
+        sh.g32[2 * p + 1] = to_f4(gv + 4);
+    }
+    if (want_bounds) {
+        double bv[8] = {mx[0], mx[1], mx[2], mx[3], mn[0], mn[1], mn[2], mn[3]};
+        store8(qmm, p, bv);
+        if (sh.qmm32) {
+            sh.qmm32[2 * p] = to_f4(bv);
+            sh.qmm32[2 * p + 1] = to_f4(bv + 4);
+        }
+    }
+}
+
+hipError_t launch_grad0_lds(hipStream_t st, const DevCloud &c, const double2 *q, double2 *g,
+                            double2 *qmm, int want_bounds, Shadow sh) {
+    const size_t shmem = (size_t)min(c.max_slots, kCap0) * 48;
+    hipLaunchKernelGGL(k_grad0_lds, dim3(num_blocks(c.n)), dim3(kBlock), shmem, st, c, q, g, qmm,
+                       want_bounds, sh);
+    return hipGetLastError();
+}
+
+// inner iteration: the least squares of eq. (29) is linear in its data, so
+//   g^k = LS(dq_i) - 1/2 LS(d.(g^{k-1}_i - g^{k-1}_p)) = g0 - 1/2 LS(...)
+// and only the previous iterate is gathered.  slot record = g (4 x double2)
+// and (x, y).
+__global__ void __launch_bounds__(kBlock) k_gradk_lds(DevCloud cl, const double2 *__restrict__ g0,
+                                                      const double2 *__restrict__ gprev,
+                                                      double2 *__restrict__ gnext,
+                                                      float4 *__restrict__ g32) {
+    extern __shared__ double2 lds[];
+    const int n = cl.n;
+    const int t = logical_block();
+    const int base = t * kBlock;
+    const int h0 = cl.halo_ptr[t], nh = cl.halo_ptr[t + 1] - h0;
+    const int nown = min(kBlock, n - base);
+    const bool in_lds = kBlock + nh <= kCapK;
+    if (in_lds) {
+        for (int s = threadIdx.x; s < kBlock + nh; s += kBlock) {
+            int pt;
+            if (s < kBlock) {
+                if (s >= nown) continue;
+                pt = base + s;
+            } else {
+                pt = cl.halo_idx[h0 + s - kBlock];
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) lds[5 * s + m] = gprev[4 * pt + m];
+            lds[5 * s + 4] = cl.xy[pt];
+        }
+    }
+    __syncthreads();
+    const int j = threadIdx.x;
+    if (j >= nown) return;
+    const int p = base + j;
+    double gp[8];
+    load8(gprev, p, gp);
+    const double2 P = cl.xy[p];
+    double a = 0.0, b = 0.0, c = 0.0;
+    double sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
+    const int k1 = cl.ptr[p + 1];
+    for (int k = cl.ptr[p]; k < k1; ++k) {
+        double gi[8];
+        double2 Q;
+        if (in_lds) {
+            const int li = cl.lidx[k];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const double2 v = lds[5 * li + m];
+                gi[2 * m] = v.x;
+                gi[2 * m + 1] = v.y;
+            }
+            Q = lds[5 * li + 4];
+        } else {
+            const int i = cl.idx[k];
+            load8(gprev, i, gi);
+            Q = cl.xy[i];
+        }
+        const double dx = Q.x - P.x, dy = Q.y - P.y;
+        a += dx * dx;
+        b += dx * dy;
+        c += dy * dy;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double f = dx * (gi[r] - gp[r]) + dy * (gi[4 + r] - gp[4 + r]);
+            sx[r] += dx * f;
+            sy[r] += dy * f;
+        }
+    }
+    const double D = a * c - b * b;
+    double gz[8], gv[8];
+    load8(g0, p, gz);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        gv[r] = gz[r] - 0.5 * ((c * sx[r] - b * sy[r]) / D);
+        gv[4 + r] = gz[4 + r] - 0.5 * ((a * sy[r] - b * sx[r]) / D);
+    }
+    store8(gnext, p, gv);
+    if (g32) {
+        g32[2 * p] = to_f4(gv);
+        g32[2 * p + 1] = to_f4(gv + 4);
+    }
+}
+
+hipError_t launch_gradk_lds(hipStream_t st, const DevCloud &c, const double2 *g0,
+                            const double2 *gprev, double2 *gnext, float4 *g32) {
+    const size_t shmem = (size_t)min(c.max_slots, kCapK) * 80;
+    hipLaunchKernelGGL(k_gradk_lds, dim3(num_blocks(c.n)), dim3(kBlock), shmem, st, c, g0, gprev,
+                       gnext, g32);
     return hipGetLastError();
 }
 
@@ -396,21 +616,36 @@ hipError_t launch_gradk(hipStream_t st, const DevCloud &c, const double2 *q, con
 namespace {
 
 struct Prim {
-    double rho, u1, u2, p, sqb, rhoe;
+    double rho, u1, u2, p, sqb, isqb, rhoe;
 };
 
 // q~ -> primitive state (inverse of eq. (26)); false if q4 >= 0 or the
-// result is not finite (the Maxwellian of q~ does not exist).
+// result is not finite (the Maxwellian of q~ does not exist).  One division
+// (1/(2 beta)), one square root and one exponential: 1/sqrt(beta) =
+// 2 sqrt(beta) / (2 beta), and beta^(-1/(gamma-1)) = (1/sqrt(beta))^m.
+// The per-state formulas below are written with explicit fma and no implicit
+// contraction, so that two reconstructed states that are bitwise equal give
+// bitwise equal fluxes (uniform flow keeps R = 0 exactly).
+template <int POW>
 __device__ __forceinline__ bool q_to_prim(const double qt[4], const FlowParams &fp, Prim &s) {
+#pragma clang fp contract(off)
     const double beta = -0.5 * qt[3];
-    const double inv2b = 1.0 / (2.0 * beta);
+    const double inv2b = -1.0 / qt[3];
     s.u1 = qt[1] * inv2b;
     s.u2 = qt[2] * inv2b;
-    const double uu = s.u1 * s.u1 + s.u2 * s.u2;
-    s.rho = exp(qt[0] - log(beta) * fp.gm1inv + beta * uu);
-    s.p = s.rho * inv2b;
+    const double uu = fma(s.u1, s.u1, s.u2 * s.u2);
     s.sqb = sqrt(beta);
-    s.rhoe = s.p * fp.gm1inv + 0.5 * s.rho * uu;
+    s.isqb = (2.0 * s.sqb) * inv2b;
+    if (POW > 0) {
+        double pw = s.isqb;
+#pragma unroll
+        for (int j = 1; j < POW; ++j) pw *= s.isqb;
+        s.rho = exp(fma(beta, uu, qt[0])) * pw;
+    } else {
+        s.rho = exp(fma(beta, uu, fma(-log(beta), fp.gm1inv, qt[0])));
+    }
+    s.p = s.rho * inv2b;
+    s.rhoe = fma(s.p, fp.gm1inv, (0.5 * s.rho) * uu);
     return (qt[3] < 0.0) && isfinite(s.rho) && isfinite(s.p) && isfinite(s.u1) &&
            isfinite(s.u2);
 }
@@ -422,16 +657,19 @@ __device__ __forceinline__ bool q_to_prim(const double qt[4], const FlowParams &
 //        (p + rho e) u_e A + sg (p/2 + rho e) B].
 __device__ __forceinline__ void split_flux(const Prim &s, double ex, double ey, double sg,
                                            double G[4]) {
+#pragma clang fp contract(off)
     constexpr double kHalfRsqrtPi = 0.28209479177387814347;  // 1 / (2 sqrt(pi))
-    const double ue = s.u1 * ex + s.u2 * ey;
+    const double ue = fma(s.u1, ex, s.u2 * ey);
     const double S = ue * s.sqb;
     const double A = 0.5 * erfc(-sg * S);
-    const double B = exp(-S * S) * kHalfRsqrtPi / s.sqb;
-    const double mass = s.rho * (ue * A + sg * B);
+    const double B = (exp(-(S * S)) * kHalfRsqrtPi) * s.isqb;
+    const double sB = sg * B;
+    const double mass = s.rho * fma(ue, A, sB);
+    const double pA = s.p * A;
     G[0] = mass;
-    G[1] = s.u1 * mass + s.p * A * ex;
-    G[2] = s.u2 * mass + s.p * A * ey;
-    G[3] = (s.p + s.rhoe) * ue * A + sg * (0.5 * s.p + s.rhoe) * B;
+    G[1] = fma(s.u1, mass, pA * ex);
+    G[2] = fma(s.u2, mass, pA * ey);
+    G[3] = fma((s.p + s.rhoe) * ue, A, (fma(0.5, s.p, s.rhoe)) * sB);
 }
 
 // Venkatakrishnan limiter value for the increment delta of one component.
@@ -457,7 +695,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // then the wall projection, q of the new state into qnext, and at stage 4
 // the next iteration's Un and time step.  Stage 1 also writes one partial
 // sum of R_c^2 per workgroup (residual norm).
-template <bool LIMITER>
+template <bool LIMITER, int POW>
 __global__ void __launch_bounds__(kBlock) k_flux(DevCloud cl, FlowParams fp, int stage,
                                                  const double2 *__restrict__ q,
                                                  const double2 *__restrict__ g,
@@ -466,7 +704,8 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevCloud cl, FlowParams fp, int
                                                  double *__restrict__ dt,
                                                  double2 *__restrict__ qnext,
                                                  double *__restrict__ Rout,
-                                                 double *__restrict__ partial, int *err) {
+                                                 double *__restrict__ partial,
+                                                 float4 *__restrict__ q32next, int *err) {
     const int n = cl.n;
     const int p = point_id();
     double R[4] = {0.0, 0.0, 0.0, 0.0};
@@ -476,7 +715,10 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevCloud cl, FlowParams fp, int
         double qp[4];
         load4(q, p, qp);
         if (kd == kOuter) {
-            if (stage > 0) store4(qnext, p, qp);  // held at the far-field state
+            if (stage > 0) {  // held at the far-field state
+                store4(qnext, p, qp);
+                if (q32next) q32next[p] = to_f4(qp);
+            }
             if (Rout) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) Rout[(size_t)r * n + p] = 0.0;
@@ -524,8 +766,8 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevCloud cl, FlowParams fp, int
                     }
                 }
                 Prim si, s0;
-                ok &= q_to_prim(qti, fp, si);
-                ok &= q_to_prim(qt0, fp, s0);
+                ok &= q_to_prim<POW>(qti, fp, si);
+                ok &= q_to_prim<POW>(qt0, fp, s0);
                 if (f & (kSPlus | kSMinus)) {
                     const bool plus = (f & kSPlus) != 0;
                     const double sg = plus ? 1.0 : -1.0;
@@ -576,6 +818,7 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevCloud cl, FlowParams fp, int
                     qq[3] = -1.0;
                 }
                 store4(qnext, p, qq);
+                if (q32next) q32next[p] = to_f4(qq);
                 if (stage == 4) {
 #pragma unroll
                     for (int c = 0; c < 4; ++c) Un[(size_t)c * n + p] = v[c];
@@ -606,14 +849,262 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevCloud cl, FlowParams fp, int
 hipError_t launch_flux(hipStream_t st, const DevCloud &c, const FlowParams &fp, int stage,
                        const double2 *q, const double2 *g, const double2 *qmm, double *U,
                        double *Un, double *dt, double2 *qnext, double *Rout, double *partial,
-                       int *err) {
+                       float4 *q32next, int *err) {
     const dim3 grid(num_blocks(c.n)), block(kBlock);
-    if (fp.limiter)
-        hipLaunchKernelGGL(k_flux<true>, grid, block, 0, st, c, fp, stage, q, g, qmm, U, Un, dt,
-                           qnext, Rout, partial, err);
-    else
-        hipLaunchKernelGGL(k_flux<false>, grid, block, 0, st, c, fp, stage, q, g, qmm, U, Un, dt,
-                           qnext, Rout, partial, err);
+#define QL_FLUX_LAUNCH(LIM, POW)                                                               \
+    hipLaunchKernelGGL((k_flux<LIM, POW>), grid, block, 0, st, c, fp, stage, q, g, qmm, U, Un, \
+                       dt, qnext, Rout, partial, q32next, err)
+    if (fp.sqrt_pow == 5) {  // gamma = 1.4
+        if (fp.limiter) QL_FLUX_LAUNCH(true, 5);
+        else QL_FLUX_LAUNCH(false, 5);
+    } else {
+        if (fp.limiter) QL_FLUX_LAUNCH(true, 0);
+        else QL_FLUX_LAUNCH(false, 0);
+    }
+#undef QL_FLUX_LAUNCH
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Mixed precision flux residual + Runge-Kutta stage.  The reconstruction
+// (eq. (28)), the limiter and the split fluxes run in FP32 from the FP32
+// shadows of q, its derivatives and its bounds, using the hardware FP32
+// exp / sqrt / reciprocal; the geometry, the least-squares weights, the
+// residual sums and the state update stay FP64.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct PrimF {
+    float rho, u1, u2, p, sqb, isqb, rhoe;
+};
+
+template <int POW>
+__device__ __forceinline__ bool q_to_prim_f(const float qt[4], float gm1inv, PrimF &s) {
+#pragma clang fp contract(off)
+    const float beta = -0.5f * qt[3];
+    const float inv2b = -1.0f / qt[3];
+    s.u1 = qt[1] * inv2b;
+    s.u2 = qt[2] * inv2b;
+    const float uu = fmaf(s.u1, s.u1, s.u2 * s.u2);
+    s.sqb = sqrtf(beta);
+    s.isqb = (2.0f * s.sqb) * inv2b;
+    if (POW > 0) {
+        float pw = s.isqb;
+#pragma unroll
+        for (int j = 1; j < POW; ++j) pw *= s.isqb;
+        s.rho = __expf(fmaf(beta, uu, qt[0])) * pw;
+    } else {
+        s.rho = __expf(fmaf(beta, uu, fmaf(-__logf(beta), gm1inv, qt[0])));
+    }
+    s.p = s.rho * inv2b;
+    s.rhoe = fmaf(s.p, gm1inv, (0.5f * s.rho) * uu);
+    return (qt[3] < 0.0f) && isfinite(s.rho) && isfinite(s.p) && isfinite(s.u1) &&
+           isfinite(s.u2);
+}
+
+__device__ __forceinline__ void split_flux_f(const PrimF &s, float ex, float ey, float sg,
+                                             float G[4]) {
+#pragma clang fp contract(off)
+    constexpr float kHalfRsqrtPi = 0.28209479177387814347f;
+    const float ue = fmaf(s.u1, ex, s.u2 * ey);
+    const float S = ue * s.sqb;
+    const float A = 0.5f * erfcf(-sg * S);
+    const float B = (__expf(-(S * S)) * kHalfRsqrtPi) * s.isqb;
+    const float sB = sg * B;
+    const float mass = s.rho * fmaf(ue, A, sB);
+    const float pA = s.p * A;
+    G[0] = mass;
+    G[1] = fmaf(s.u1, mass, pA * ex);
+    G[2] = fmaf(s.u2, mass, pA * ey);
+    G[3] = fmaf((s.p + s.rhoe) * ue, A, (fmaf(0.5f, s.p, s.rhoe)) * sB);
+}
+
+__device__ __forceinline__ float venkat_f(float delta, float q, float qmx, float qmn, float eps2) {
+    const float D = (delta > 0.0f) ? (qmx - q) : (qmn - q);
+    const float num = (D * D + eps2) + 2.0f * delta * D;
+    const float den = D * D + 2.0f * delta * delta + delta * D + eps2;
+    return (den == 0.0f) ? 1.0f : num / den;
+}
+
+__device__ __forceinline__ void unpack(const float4 a, float *v) {
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+
+}  // namespace
+
+template <bool LIMITER, int POW>
+__global__ void __launch_bounds__(kBlock) k_flux_mixed(
+    DevCloud cl, FlowParams fp, int stage, const double2 *__restrict__ q,
+    const float4 *__restrict__ q32, const float4 *__restrict__ g32,
+    const float4 *__restrict__ qmm32, double *__restrict__ U, double *__restrict__ Un,
+    double *__restrict__ dt, double2 *__restrict__ qnext, float4 *__restrict__ q32next,
+    double *__restrict__ Rout, double *__restrict__ partial, int *err) {
+    const int n = cl.n;
+    const int p = point_id();
+    double R[4] = {0.0, 0.0, 0.0, 0.0};
+    bool updated = false;
+    if (p < n) {
+        const uint8_t kd = cl.kind[p];
+        if (kd == kOuter) {
+            if (stage > 0) {
+                double qp[4];
+                load4(q, p, qp);
+                store4(qnext, p, qp);
+                q32next[p] = q32[p];
+            }
+            if (Rout) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Rout[(size_t)r * n + p] = 0.0;
+            }
+        } else {
+            updated = true;
+            const float gm1inv = (float)fp.gm1inv;
+            const float vk = (float)fp.venkat_k;
+            const double2 P = cl.xy[p], N = cl.nrm[p];
+            const double tx = N.y, ty = -N.x;
+            const float txf = (float)tx, tyf = (float)ty, nxf = (float)N.x, nyf = (float)N.y;
+            float qp[4], gp[8], bp[8];
+            unpack(q32[p], qp);
+            unpack(g32[2 * p], gp);
+            unpack(g32[2 * p + 1], gp + 4);
+            if (LIMITER) {
+                unpack(qmm32[2 * p], bp);
+                unpack(qmm32[2 * p + 1], bp + 4);
+            }
+            double w[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) w[j] = cl.lsw[8 * p + j];
+            const uint8_t fmask = (kd == kWall) ? uint8_t(~kNPlus) : uint8_t(0xff);
+            const int k1 = cl.ptr[p + 1];
+            bool ok = true;
+            for (int k = cl.ptr[p]; k < k1; ++k) {
+                const uint8_t f = cl.flag[k] & fmask;
+                if (f == 0) continue;
+                const int i = cl.idx[k];
+                const double2 Q = cl.xy[i];
+                const double dx = Q.x - P.x, dy = Q.y - P.y;
+                const double ds = dx * tx + dy * ty;
+                const double dn = dx * N.x + dy * N.y;
+                const float dxf = (float)dx, dyf = (float)dy;
+                float qi[4], gi[8], qti[4], qt0[4];
+                unpack(q32[i], qi);
+                unpack(g32[2 * i], gi);
+                unpack(g32[2 * i + 1], gi + 4);
+                if (LIMITER) {
+                    float bi[8];
+                    unpack(qmm32[2 * i], bi);
+                    unpack(qmm32[2 * i + 1], bi + 4);
+                    const float e = vk * sqrtf(dxf * dxf + dyf * dyf);
+                    const float eps2 = e * e * e;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float di = -0.5f * (dxf * gi[r] + dyf * gi[4 + r]);
+                        const float d0 = -0.5f * (dxf * gp[r] + dyf * gp[4 + r]);
+                        qti[r] = qi[r] + venkat_f(di, qi[r], bi[r], bi[4 + r], eps2) * di;
+                        qt0[r] = qp[r] + venkat_f(d0, qp[r], bp[r], bp[4 + r], eps2) * d0;
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        qti[r] = qi[r] - 0.5f * (dxf * gi[r] + dyf * gi[4 + r]);
+                        qt0[r] = qp[r] - 0.5f * (dxf * gp[r] + dyf * gp[4 + r]);
+                    }
+                }
+                PrimF si, s0;
+                ok &= q_to_prim_f<POW>(qti, gm1inv, si);
+                ok &= q_to_prim_f<POW>(qt0, gm1inv, s0);
+                if (f & (kSPlus | kSMinus)) {
+                    const bool plus = (f & kSPlus) != 0;
+                    const float sg = plus ? 1.0f : -1.0f;
+                    const double wt = ds * (plus ? w[0] : w[2]) - dn * (plus ? w[1] : w[3]);
+                    float Gi[4], G0[4];
+                    split_flux_f(si, txf, tyf, sg, Gi);
+                    split_flux_f(s0, txf, tyf, sg, G0);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) R[r] += wt * (double)(Gi[r] - G0[r]);
+                }
+                if (f & (kNPlus | kNMinus)) {
+                    const bool plus = (f & kNPlus) != 0;
+                    const float sg = plus ? 1.0f : -1.0f;
+                    const double wt = dn * (plus ? w[4] : w[6]) - ds * (plus ? w[5] : w[7]);
+                    float Gi[4], G0[4];
+                    split_flux_f(si, nxf, nyf, sg, Gi);
+                    split_flux_f(s0, nxf, nyf, sg, G0);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) R[r] += wt * (double)(Gi[r] - G0[r]);
+                }
+            }
+            if (!ok) report(err, p, kErrPositivity);
+            if (Rout) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Rout[(size_t)r * n + p] = R[r];
+            }
+            if (stage > 0) {
+                const double h = 0.5 * dt[p];
+                double v[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const double u = U[(size_t)c * n + p];
+                    if (stage == 3)
+                        v[c] = (2.0 / 3.0) * Un[(size_t)c * n + p] + (1.0 / 3.0) * (u - h * R[c]);
+                    else
+                        v[c] = u - h * R[c];
+                }
+                if (kd == kWall) wall_project(v, N);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) U[(size_t)c * n + p] = v[c];
+                double qq[4];
+                const int e = cons_to_q(v, fp, qq);
+                if (e != kErrNone) {
+                    report(err, p, e);
+                    qq[0] = qq[1] = qq[2] = 0.0;
+                    qq[3] = -1.0;
+                }
+                store4(qnext, p, qq);
+                q32next[p] = to_f4(qq);
+                if (stage == 4) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) Un[(size_t)c * n + p] = v[c];
+                    dt[p] = local_dt(v, cl.dmin[p], fp);
+                }
+            }
+        }
+    }
+    if (partial != nullptr) {
+        __shared__ double red[kBlock / 64][4];
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double sres = wave_sum(updated ? R[c] * R[c] : 0.0);
+            if (lane == 0) red[wv][c] = sres;
+        }
+        __syncthreads();
+        if (threadIdx.x < 4) {
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < kBlock / 64; ++j) acc += red[j][threadIdx.x];
+            partial[4 * logical_block() + threadIdx.x] = acc;
+        }
+    }
+}
+
+hipError_t launch_flux_mixed(hipStream_t st, const DevCloud &c, const FlowParams &fp, int stage,
+                             const double2 *q, const float4 *q32, const float4 *g32,
+                             const float4 *qmm32, double *U, double *Un, double *dt,
+                             double2 *qnext, float4 *q32next, double *Rout, double *partial,
+                             int *err) {
+    const dim3 grid(num_blocks(c.n)), block(kBlock);
+#define QL_FLUXM_LAUNCH(LIM, POW)                                                             \
+    hipLaunchKernelGGL((k_flux_mixed<LIM, POW>), grid, block, 0, st, c, fp, stage, q, q32, g32, \
+                       qmm32, U, Un, dt, qnext, q32next, Rout, partial, err)
+    if (fp.sqrt_pow == 5) {
+        if (fp.limiter) QL_FLUXM_LAUNCH(true, 5);
+        else QL_FLUXM_LAUNCH(false, 5);
+    } else {
+        if (fp.limiter) QL_FLUXM_LAUNCH(true, 0);
+        else QL_FLUXM_LAUNCH(false, 0);
+    }
+#undef QL_FLUXM_LAUNCH
     return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -62,7 +63,11 @@ struct ql_solver {
     int *ptr = nullptr, *idx = nullptr, *dperm = nullptr, *wall = nullptr;
     double *lsw = nullptr, *dmin = nullptr;
     double *U = nullptr, *Un = nullptr, *dt = nullptr, *R = nullptr, *tmp = nullptr;
-    double2 *q[2] = {nullptr, nullptr}, *g[2] = {nullptr, nullptr}, *qmm = nullptr;
+    double2 *q[2] = {nullptr, nullptr}, *g[3] = {nullptr, nullptr, nullptr}, *qmm = nullptr;
+    float4 *q32[2] = {nullptr, nullptr}, *g32 = nullptr, *qmm32 = nullptr;  // FP32 shadows
+    int *halo_ptr = nullptr, *halo_idx = nullptr;
+    uint16_t *lidx = nullptr;
+    int max_slots = 0;
     double *partial = nullptr, *reshist = nullptr, *fscratch = nullptr, *fout = nullptr;
     int reshist_cap = 0;
     int *errw = nullptr;
@@ -71,6 +76,7 @@ struct ql_solver {
     double last_res[4] = {0, 0, 0, 0};
 
     bool timing = false;
+    bool untiled = false;  // QLSKUM_UNTILED=1: gather straight from memory (A/B checks)
     std::vector<TimedLaunch> pending;
     std::vector<hipEvent_t> event_pool;
     double tsum[4] = {0, 0, 0, 0};
@@ -114,8 +120,10 @@ void free_cloud(ql_solver *s) {
     dfree(s->xy); dfree(s->nrm); dfree(s->kind); dfree(s->flag); dfree(s->ptr); dfree(s->idx);
     dfree(s->dperm); dfree(s->wall); dfree(s->lsw); dfree(s->dmin); dfree(s->U); dfree(s->Un);
     dfree(s->dt); dfree(s->R); dfree(s->tmp); dfree(s->q[0]); dfree(s->q[1]); dfree(s->g[0]);
-    dfree(s->g[1]); dfree(s->qmm); dfree(s->partial); dfree(s->reshist); dfree(s->fscratch);
-    dfree(s->fout); dfree(s->errw);
+    dfree(s->g[1]); dfree(s->g[2]); dfree(s->qmm); dfree(s->partial); dfree(s->reshist);
+    dfree(s->fscratch); dfree(s->fout); dfree(s->errw); dfree(s->halo_ptr); dfree(s->halo_idx);
+    dfree(s->lidx); dfree(s->q32[0]); dfree(s->q32[1]); dfree(s->g32); dfree(s->qmm32);
+    s->max_slots = 0;
     s->reshist_cap = 0;
     s->has_cloud = s->has_state = s->has_eval = s->has_res = false;
     s->n = 0;
@@ -163,6 +171,45 @@ std::vector<int> hilbert_order(int n, const double *x, const double *y) {
     return perm;
 }
 
+// Tiles of kBlock consecutive points: the sorted list of each tile's halo
+// (neighbours outside the tile) and every entry's slot in the tile's LDS
+// image.  Returns the largest image (own slots + halo), or INT_MAX when a
+// slot would not fit 16 bits.
+int build_tiles(int n, const std::vector<int> &ptr, const std::vector<int> &idx,
+                std::vector<int> &hptr, std::vector<int> &hidx, std::vector<uint16_t> &lidx) {
+    const int ntile = num_blocks(n);
+    hptr.assign(ntile + 1, 0);
+    hidx.clear();
+    lidx.assign(idx.size(), 0);
+    std::vector<int> stamp(n, -1), slot(n, 0), h;
+    int max_slots = 0;
+    for (int t = 0; t < ntile; ++t) {
+        const int base = t * kBlock, end = std::min(n, base + kBlock);
+        h.clear();
+        for (int p = base; p < end; ++p)
+            for (int k = ptr[p]; k < ptr[p + 1]; ++k) {
+                const int i = idx[k];
+                if ((i < base || i >= end) && stamp[i] != t) {
+                    stamp[i] = t;
+                    h.push_back(i);
+                }
+            }
+        std::sort(h.begin(), h.end());
+        const int slots = kBlock + (int)h.size();
+        if (slots > 65535) return INT_MAX;
+        for (size_t j = 0; j < h.size(); ++j) slot[h[j]] = kBlock + (int)j;
+        for (int p = base; p < end; ++p)
+            for (int k = ptr[p]; k < ptr[p + 1]; ++k) {
+                const int i = idx[k];
+                lidx[k] = (uint16_t)((i >= base && i < end) ? i - base : slot[i]);
+            }
+        hidx.insert(hidx.end(), h.begin(), h.end());
+        hptr[t + 1] = (int)hidx.size();
+        max_slots = std::max(max_slots, slots);
+    }
+    return max_slots;
+}
+
 DevCloud dev_cloud(const ql_solver *s) {
     DevCloud c;
     c.n = s->n;
@@ -174,6 +221,10 @@ DevCloud dev_cloud(const ql_solver *s) {
     c.flag = s->flag;
     c.lsw = s->lsw;
     c.dmin = s->dmin;
+    c.halo_ptr = s->halo_ptr;
+    c.halo_idx = s->halo_idx;
+    c.lidx = s->lidx;
+    c.max_slots = s->max_slots;
     return c;
 }
 
@@ -185,6 +236,9 @@ FlowParams flow_params(const ql_solver *s) {
     f.venkat_k = s->prm.venkat_k;
     f.n_inner = s->prm.n_inner;
     f.limiter = s->prm.limiter;
+    const double m = 2.0 / (s->prm.gamma - 1.0);
+    const double mr = std::nearbyint(m);
+    f.sqrt_pow = (std::fabs(m - mr) <= 1e-12 * m && mr >= 1.0 && mr <= 16.0) ? (int)mr : 0;
     return f;
 }
 
@@ -197,7 +251,8 @@ int check_params(ql_solver *s, const ql_params *p) {
     if (p->n_inner < 0 || p->n_inner > 1000) return fail(s, QL_EINVAL, "n_inner out of range");
     if (p->limiter != 0 && p->limiter != 1) return fail(s, QL_EINVAL, "limiter must be 0 or 1");
     if (p->limiter && !(p->venkat_k > 0.0)) return fail(s, QL_EINVAL, "venkat_k must be > 0");
-    if (p->precision != 0) return fail(s, QL_EINVAL, "precision must be 0 (FP64)");
+    if (p->precision != 0 && p->precision != 1)
+        return fail(s, QL_EINVAL, "precision must be 0 (FP64) or 1 (mixed)");
     if (p->reorder != 0 && p->reorder != 1) return fail(s, QL_EINVAL, "reorder must be 0 or 1");
     return QL_OK;
 }
@@ -274,17 +329,39 @@ struct Timer {
 // One stage's q-derivatives: first pass + n_inner Jacobi iterations; leaves
 // the final iterate in g[gfin].
 int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds) {
+    const bool tiled = !s->untiled;
+    const bool lds0 = tiled && lds_fits_grad0(c), ldsk = tiled && lds_fits_gradk(c);
+    // first pass into g[2] when the inner iterations run tiled (they read g0)
+    const int first = (ldsk && s->prm.n_inner > 0) ? 2 : 0;
+    // mixed precision: the last pass also writes the FP32 shadow of g, the
+    // first pass the FP32 shadow of the bounds
+    const bool mixed = s->prm.precision == 1;
+    Shadow sh{nullptr, nullptr, nullptr};
+    if (mixed) {
+        sh.qmm32 = s->qmm32;
+        if (s->prm.n_inner == 0) sh.g32 = s->g32;
+    }
     {
         Timer t(s, 0);
-        HIPCHK(s, launch_grad0(s->stream, c, s->q[s->qcur], s->g[0], s->qmm, want_bounds ? 1 : 0));
+        if (lds0)
+            HIPCHK(s, launch_grad0_lds(s->stream, c, s->q[s->qcur], s->g[first], s->qmm,
+                                       want_bounds ? 1 : 0, sh));
+        else
+            HIPCHK(s, launch_grad0(s->stream, c, s->q[s->qcur], s->g[first], s->qmm,
+                                   want_bounds ? 1 : 0, sh));
         t.done();
     }
-    int cur = 0;
+    int cur = first;
     for (int k = 0; k < s->prm.n_inner; ++k) {
+        const int nxt = (cur == 0) ? 1 : 0;
+        float4 *g32 = (mixed && k == s->prm.n_inner - 1) ? s->g32 : nullptr;
         Timer t(s, 1);
-        HIPCHK(s, launch_gradk(s->stream, c, s->q[s->qcur], s->g[cur], s->g[1 - cur]));
+        if (ldsk)
+            HIPCHK(s, launch_gradk_lds(s->stream, c, s->g[2], s->g[cur], s->g[nxt], g32));
+        else
+            HIPCHK(s, launch_gradk(s->stream, c, s->q[s->qcur], s->g[cur], s->g[nxt], g32));
         t.done();
-        cur = 1 - cur;
+        cur = nxt;
     }
     s->gfin = cur;
     return QL_OK;
@@ -297,7 +374,21 @@ int prep_state(ql_solver *s) {
     int st = reset_err(s);
     if (st) return st;
     s->qcur = 0;
-    HIPCHK(s, launch_prep(s->stream, c, fp, s->U, s->Un, s->q[0], s->dt, s->errw));
+    HIPCHK(s, launch_prep(s->stream, c, fp, s->U, s->Un, s->q[0], s->dt, s->q32[0], s->errw));
+    return QL_OK;
+}
+
+// One flux-residual launch (stage 0: evaluate into R; 1..4: RK stage).
+int launch_stage(ql_solver *s, const DevCloud &c, const FlowParams &fp, int stage, double *Rout,
+                 double *partial) {
+    const int a = s->qcur, b = 1 - s->qcur;
+    if (s->prm.precision == 1)
+        HIPCHK(s, launch_flux_mixed(s->stream, c, fp, stage, s->q[a], s->q32[a], s->g32, s->qmm32,
+                                    s->U, s->Un, s->dt, s->q[b], s->q32[b], Rout, partial,
+                                    s->errw));
+    else
+        HIPCHK(s, launch_flux(s->stream, c, fp, stage, s->q[a], s->g[s->gfin], s->qmm, s->U,
+                              s->Un, s->dt, s->q[b], Rout, partial, s->q32[b], s->errw));
     return QL_OK;
 }
 
@@ -333,6 +424,7 @@ int ql_create(ql_solver **out, int32_t device, void *hip_stream) {
     if (!s) return QL_ENOMEM;
     ql_default_params(&s->prm);
     s->device = device;
+    if (const char *e = std::getenv("QLSKUM_UNTILED")) s->untiled = (e[0] == '1');
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
         delete s;
@@ -459,7 +551,10 @@ int ql_upload_cloud(ql_solver *s, int64_t n64, const double *x, const double *y,
     HIPCHK(s, dalloc(&s->tmp, (size_t)4 * n));
     HIPCHK(s, dalloc(&s->q[0], (size_t)2 * n)); HIPCHK(s, dalloc(&s->q[1], (size_t)2 * n));
     HIPCHK(s, dalloc(&s->g[0], (size_t)4 * n)); HIPCHK(s, dalloc(&s->g[1], (size_t)4 * n));
+    HIPCHK(s, dalloc(&s->g[2], (size_t)4 * n));
     HIPCHK(s, dalloc(&s->qmm, (size_t)4 * n));
+    HIPCHK(s, dalloc(&s->q32[0], n)); HIPCHK(s, dalloc(&s->q32[1], n));
+    HIPCHK(s, dalloc(&s->g32, (size_t)2 * n)); HIPCHK(s, dalloc(&s->qmm32, (size_t)2 * n));
     HIPCHK(s, dalloc(&s->partial, (size_t)4 * nblk));
     HIPCHK(s, dalloc(&s->fscratch, (size_t)3 * std::max<size_t>(hwall.size(), 1)));
     HIPCHK(s, dalloc(&s->fout, 2)); HIPCHK(s, dalloc(&s->errw, 2));
@@ -474,6 +569,26 @@ int ql_upload_cloud(ql_solver *s, int64_t n64, const double *x, const double *y,
     HIPCHK(s, hipMemcpyAsync(s->dperm, perm.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
     if (!hwall.empty())
         HIPCHK(s, hipMemcpyAsync(s->wall, hwall.data(), sizeof(int) * hwall.size(), hipMemcpyHostToDevice, st));
+    {
+        std::vector<int> thptr, thidx;
+        std::vector<uint16_t> tlidx;
+        s->max_slots = build_tiles(n, hptr, hidx, thptr, thidx, tlidx);
+        if (s->max_slots == INT_MAX) {
+            s->max_slots = 1 << 30;  // no tiled kernels for this cloud
+        } else {
+            HIPCHK(s, dalloc(&s->halo_ptr, thptr.size()));
+            HIPCHK(s, dalloc(&s->halo_idx, thidx.size()));
+            HIPCHK(s, dalloc(&s->lidx, tlidx.size()));
+            HIPCHK(s, hipMemcpy(s->halo_ptr, thptr.data(), sizeof(int) * thptr.size(),
+                                hipMemcpyHostToDevice));
+            if (!thidx.empty())
+                HIPCHK(s, hipMemcpy(s->halo_idx, thidx.data(), sizeof(int) * thidx.size(),
+                                    hipMemcpyHostToDevice));
+            if (!tlidx.empty())
+                HIPCHK(s, hipMemcpy(s->lidx, tlidx.data(), sizeof(uint16_t) * tlidx.size(),
+                                    hipMemcpyHostToDevice));
+        }
+    }
     s->perm.swap(perm);
     s->inv.swap(inv);
     s->eperm.swap(eperm);
@@ -578,9 +693,8 @@ int ql_step(ql_solver *s, int32_t n_iter, double *res_hist) {
             st = run_gradients(s, c, fp.limiter != 0);
             if (st) return st;
             Timer t(s, 2);
-            HIPCHK(s, launch_flux(s->stream, c, fp, rk, s->q[s->qcur], s->g[s->gfin], s->qmm, s->U,
-                                  s->Un, s->dt, s->q[1 - s->qcur], nullptr,
-                                  rk == 1 ? s->partial : nullptr, s->errw));
+            st = launch_stage(s, c, fp, rk, nullptr, rk == 1 ? s->partial : nullptr);
+            if (st) return st;
             t.done();
             s->qcur = 1 - s->qcur;
         }
@@ -618,11 +732,8 @@ int ql_evaluate(ql_solver *s) {
     if (st) return st;
     st = run_gradients(s, c, true);
     if (st) return st;
-    if (!fp.limiter) {
-        // bounds are always produced for inspection; the residual ignores them
-    }
-    HIPCHK(s, launch_flux(s->stream, c, fp, 0, s->q[s->qcur], s->g[s->gfin], s->qmm, s->U, s->Un,
-                          s->dt, s->q[1 - s->qcur], s->R, nullptr, s->errw));
+    st = launch_stage(s, c, fp, 0, s->R, nullptr);
+    if (st) return st;
     st = sync_and_check(s, "evaluate");
     harvest_timing(s);
     s->has_eval = (st == QL_OK);

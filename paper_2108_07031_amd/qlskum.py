@@ -11,6 +11,11 @@ import os
 
 import numpy as np
 
+try:  # torch first: the process then uses torch's HIP runtime for both
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover - torch is only plumbing
+    torch = None
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqlskum.so")
 

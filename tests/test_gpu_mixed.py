@@ -1,0 +1,84 @@
+"""Mixed precision path (precision = 1): reconstruction, limiter and split
+fluxes in FP32; q-derivatives, least-squares weights, residual sums and the
+state update in FP64.
+
+Bounds: the q-derivatives are the FP64 ones bit for bit; uniform flow still
+gives R = 0 exactly (identical reconstructed states give identical FP32
+fluxes); one evaluation's residual lies within 2e-3 normwise of the FP64
+oracle (each perturbation G(q~_i) - G(q~_0) is a difference of nearby
+values, so FP32 rounding of the two states, ~6e-8 relative, is amplified by
+1/(h |grad G|/|G|), up to ~3e3 on these clouds); converged lift and drag
+within 1e-4 of the FP64 solution.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests._common import cloud, normwise_rel, smooth_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ql():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2108_07031_amd import qlskum
+    return qlskum
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def test_mixed_freestream_exact(ql):
+    _say("mixed freestream")
+    from cloudgen import random_cloud
+    for limiter in (0, 1):
+        c = random_cloud(400, seed=11)
+        o = oracle.Oracle(c, oracle.params(limiter=limiter))
+        s = ql.Solver(c, limiter=limiter, precision=1)
+        s.set_state(o.freestream(project_wall=False))
+        assert np.count_nonzero(s.evaluate()["R"]) == 0
+        s.close()
+
+
+@pytest.mark.parametrize("limiter", [0, 1])
+def test_mixed_evaluate_close_to_oracle(ql, limiter):
+    _say(f"mixed evaluate limiter={limiter}")
+    c = cloud("c1")
+    prm = dict(limiter=limiter, mach=0.85 if limiter else 0.63, alpha_deg=1.0 if limiter else 2.0)
+    U = smooth_state(c, mach=prm["mach"], alpha_deg=prm["alpha_deg"])
+    ora = oracle.Oracle(c, oracle.params(**prm)).evaluate(U)
+    s64 = ql.Solver(c, precision=0, **prm)
+    s64.set_state(U)
+    e64 = s64.evaluate()
+    s32 = ql.Solver(c, precision=1, **prm)
+    s32.set_state(U)
+    e32 = s32.evaluate()
+    np.testing.assert_array_equal(e32["g"], e64["g"])
+    err = normwise_rel(e32["R"], ora["R"])
+    _say(f"  mixed R error {err}")
+    assert np.all(err <= 2e-3), err
+    s64.close()
+    s32.close()
+
+
+def test_mixed_converged_forces(ql):
+    """9,600-point cloud, M 0.63, alpha 2: converged lift and drag of the
+    mixed path within 1e-4 of the FP64 path."""
+    _say("mixed converged forces")
+    c = cloud("c1")
+    out = {}
+    for prec in (0, 1):
+        s = ql.Solver(c, precision=prec)
+        s.init_freestream()
+        h = s.step(30000)
+        out[prec] = (s.forces(), s.fetch_state(), h)
+        _say(f"  precision {prec}: residual drop {h[-1, 0] / h[0, 0]:.2e}, cl, cd {out[prec][0]}")
+        s.close()
+    (cl0, cd0), U0, _ = out[0]
+    (cl1, cd1), U1, _ = out[1]
+    assert abs(cl1 - cl0) <= 1e-4 and abs(cd1 - cd0) <= 1e-4
+    assert normwise_rel(U1[:1], U0[:1]).max() <= 1e-3
