@@ -78,6 +78,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=("both", "fp64", "mixed"), default="both")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB MiB (reference kernel for "
+                         "hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -126,6 +129,15 @@ def main():
         elapsed = max(wall, gpu_ms / 1e3)
         return dict(flags=flags, elapsed=elapsed, ktime=ktime, hist=hist, cl=cl, cd=cd,
                     value=cloud.n * args.steps / elapsed / 1e6)
+
+    if args.copy_calibration > 0:
+        nel = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration} MiB read + written")
+        del src, dst
 
     runs = {p: timed_run(p) for p in ((0, 1) if args.precision == "both" else
                                       (0,) if args.precision == "fp64" else (1,))}

@@ -74,6 +74,10 @@ typedef struct {
                          and split fluxes in FP32, least-squares weights,
                          residual sums and the state update in FP64           */
     int32_t reorder;  /* read at upload: 0 caller order, 1 Hilbert curve        */
+    int32_t flux_lds; /* tuning: bytes of LDS in which a flux workgroup stages
+                         the records of its 64-point tile and halo (tiles that
+                         do not fit read from memory; same results either
+                         way); 0 = the library's default, at most 163840      */
 } ql_params;
 
 /* Fill *p with the defaults: gamma 1.4, M 0.63, alpha 2, CFL 0.2, 3 inner
@@ -131,8 +135,9 @@ int ql_set_state(ql_solver *s, const double *U, int32_t mem, int32_t project_wal
 /* Run n_iter pseudo-time iterations (sec. 3 Algorithm 1): per iteration the
  * local time step, four stages of four-stage third-order SSP Runge-Kutta,
  * and the residual norm of the first stage's residual.  res_hist (host,
- * nullable) receives [n_iter][4] residual norms (root mean square over the
- * interior and wall points of each component).  Enqueues on the solver's
+ * nullable) receives [n_iter][ncase][4] residual norms (root mean square
+ * over the interior and wall points of each component; ncase = 1 unless
+ * the cloud came from ql_batch_upload).  Enqueues on the solver's
  * stream and synchronises once at the end.
  * Errors: QL_ESTATE, QL_EPOSITIVITY / QL_ENONFINITE (first point of the
  * first failing launch; the state is then undefined), QL_EDEVICE. */
@@ -157,6 +162,42 @@ int ql_forces(ql_solver *s, double *cl, double *cd);
 /* Message of the last failing call on this solver ("" if none). */
 const char *ql_last_error(const ql_solver *s);
 
+/* --- batched form: many independent cases in one set of launches ------- */
+
+/* Upload ncase independent clouds, concatenated in the caller's order: case
+ * c owns caller points case_ptr[c] .. case_ptr[c+1]-1 (case_ptr[0] = 0,
+ * case_ptr[ncase] = n, every case non-empty); its neighbour lists index the
+ * concatenated arrays and stay inside the case; mach[c] and alpha_deg[c]
+ * are its freestream.  Every iteration kernel then advances all cases in
+ * one launch.  Arrays and validation as ql_upload_cloud (the library
+ * classifies the split stencils), which is the one-case form: there the
+ * freestream follows ql_set_params.  Per-case results: ql_step's res_hist
+ * becomes [n_iter][ncase][4]; ql_residual_norm and ql_forces report case 0.
+ * Errors as ql_upload_cloud. */
+int ql_batch_upload(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int64_t n,
+                    const double *x, const double *y, const double *nx, const double *ny,
+                    const uint8_t *kind, const int32_t *nbr_ptr, const int32_t *nbr_idx,
+                    const double *mach, const double *alpha_deg);
+
+/* Number of cases of the uploaded cloud.  Errors: QL_ESTATE. */
+int ql_batch_info(const ql_solver *s, int32_t *ncase);
+
+/* Iterate all cases until each one's density residual norm falls to
+ * drop x its first iteration's norm, or max_iter iterations.  Every
+ * check_every iterations the norms are read back; converged cases retire:
+ * their points stop updating and workgroups holding only retired points
+ * skip every sweep, while the other cases go on.  graph != 0 captures one
+ * iteration into a hipGraph on the solver's stream (re-captured after
+ * parameter or buffer changes) and replays it.  iters_out[c] (nullable)
+ * receives the iteration at which case c reached the drop (or the
+ * iterations run), res_out[c][4] (nullable) its last norms.
+ * Errors: as ql_step; QL_EINVAL (drop <= 0, max_iter < 0, check_every < 1). */
+int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_every, int32_t graph,
+                 int32_t *iters_out, double *res_out);
+
+/* Lift and drag of every case (as ql_forces), cl[ncase], cd[ncase]. */
+int ql_batch_forces(ql_solver *s, double *cl, double *cd);
+
 /* --- inspection and timing (tests, benchmarks) ------------------------- */
 
 /* One evaluation of the stage operator at the current state, without
@@ -164,6 +205,15 @@ const char *ql_last_error(const ql_solver *s);
  * limiter bounds, the residual R and the time step.  Fetch them with
  * ql_debug_fetch.  Errors as ql_step. */
 int ql_evaluate(ql_solver *s);
+
+/* The flux sweep's tiles (64 consecutive points of the library's order):
+ * *ntile receives their number (0 when the cloud has no tiling: every tile
+ * reads from memory), and slots[ntile], when not NULL, the records each
+ * tile's LDS image holds (its points plus its halo).  A tile is staged in
+ * LDS when slots * record bytes <= the flux_lds budget; the record is 176
+ * bytes (FP64 with limiter), 112 (FP64), 96 (mixed with limiter) or 64
+ * (mixed).  Errors: QL_EINVAL (NULL), QL_ESTATE (no cloud). */
+int ql_flux_tiles(const ql_solver *s, int32_t *ntile, int32_t *slots);
 
 /* Copy an inspection array to host memory `out` in caller order:
  *   0 q [4][n]       1 g [8][n] (q_x rows 0..3, q_y rows 4..7)

@@ -9,6 +9,10 @@ namespace ql {
 
 constexpr int kBlock = 256;  // threads per workgroup for every point sweep
 constexpr int kXcd = 8;      // MI355X accelerator complex dies
+// flux sweep: kFluxTile points per workgroup, kFluxLanes lanes per point
+constexpr int kFluxTile = 64;
+constexpr int kFluxLanes = kBlock / kFluxTile;
+static_assert(kFluxTile * kFluxLanes == kBlock, "flux tile must fill a workgroup");
 
 enum Kind : uint8_t { kInterior = 0, kWall = 1, kOuter = 2 };
 enum Split : uint8_t { kSPlus = 1, kSMinus = 2, kNPlus = 4, kNMinus = 8 };
@@ -24,15 +28,24 @@ struct DevCloud {
     const int *idx;      // [nnz]
     const uint8_t *flag; // [nnz] split membership
     const double *lsw;   // [n][8] split least-squares factors, 2 per stencil
+    const double *lsi;   // [n][3] full-stencil LS inverse (Syy, Sxy, Sxx) / Det
     const double *dmin;  // [n] distance to the nearest neighbour
-    // LDS tiling: tile t = points [t*kBlock, (t+1)*kBlock); its halo (the
-    // neighbours outside the tile) is halo_idx[halo_ptr[t] .. halo_ptr[t+1]);
-    // lidx[k] is neighbour entry k's slot in the tile's LDS image (own point
-    // j -> j, halo point h -> kBlock + h).  max_slots = largest image.
-    const int *halo_ptr;
-    const int *halo_idx;
-    const uint16_t *lidx;
-    int max_slots;
+    // LDS tiling of the point sweeps: tile t = points [t*kFluxTile,
+    // (t+1)*kFluxTile); its halo (the neighbours outside the tile) is
+    // fhalo_idx[fhalo_ptr[t] .. fhalo_ptr[t+1]); flidx[k] is neighbour entry
+    // k's slot in the tile's LDS image (own point j -> j, halo point h ->
+    // kFluxTile + h); fmax_slots = the largest image.  fhalo_ptr is null when
+    // the cloud has no tiling: every tile reads from memory.
+    const int *fhalo_ptr;
+    const int *fhalo_idx;
+    const uint16_t *flidx;
+    int fmax_slots;
+    // batched cases: case_of[p]; case_active[c] == 0 freezes case c (nullable:
+    // all active); tile_active[t] == 0 skips (64-point) tile t in every
+    // tiled sweep (nullable)
+    const int *case_of;
+    const uint8_t *case_active;
+    const uint8_t *tile_active;
 };
 
 struct FlowParams {
@@ -54,45 +67,58 @@ struct Shadow {
 // Error word on the device: err[0] = smallest failing point (INT_MAX when
 // none), err[1] = ErrCode of some failing point.
 int num_blocks(int n);
+int num_flux_tiles(int n);
 
 hipError_t launch_setup(hipStream_t st, int n, const double2 *xy, const double2 *nrm,
                         const uint8_t *kind, const int *ptr, const int *idx, uint8_t *flag,
-                        int classify, double *lsw, double *dmin, int *err);
+                        int classify, double *lsw, double *lsi, double *dmin, int *err);
 hipError_t launch_freestream(hipStream_t st, int n, const double2 *nrm, const uint8_t *kind,
-                             const double *Uinf, double *U);
+                             const int *case_of, const double *uinf, double *U);
 hipError_t launch_permute_state(hipStream_t st, int n, const double *Uuser, const int *perm,
                                 const double2 *nrm, const uint8_t *kind, int project, double *U);
 hipError_t launch_unpermute_state(hipStream_t st, int n, const double *U, const int *perm,
                                   double *Uuser);
 hipError_t launch_prep(hipStream_t st, const DevCloud &c, const FlowParams &fp, const double *U,
                        double *Un, double2 *q, double *dt, float4 *q32, int *err);
-hipError_t launch_grad0(hipStream_t st, const DevCloud &c, const double2 *q, double2 *g,
-                        double2 *qmm, int want_bounds, Shadow sh);
-hipError_t launch_gradk(hipStream_t st, const DevCloud &c, const double2 *q, const double2 *gprev,
-                        double2 *gnext, float4 *g32);
-// LDS-tiled variants (used when the tile images fit); the inner iteration
-// takes the first-pass derivatives g0 instead of q.
-bool lds_fits_grad0(const DevCloud &c);
-bool lds_fits_gradk(const DevCloud &c);
-hipError_t launch_grad0_lds(hipStream_t st, const DevCloud &c, const double2 *q, double2 *g,
-                            double2 *qmm, int want_bounds, Shadow sh);
-hipError_t launch_gradk_lds(hipStream_t st, const DevCloud &c, const double2 *g0,
-                            const double2 *gprev, double2 *gnext, float4 *g32);
+// q-derivatives (tiled like the flux sweep; lds_budget as there): first
+// pass with limiter bounds, and one inner iteration from the first pass g0
+// and the previous iterate gprev.
+hipError_t launch_grad0(hipStream_t st, const DevCloud &c, int lds_budget, const double2 *q,
+                        double2 *g, double2 *qmm, int want_bounds, Shadow sh);
+hipError_t launch_gradk(hipStream_t st, const DevCloud &c, int lds_budget, const double2 *g0,
+                        const double2 *gprev, double2 *gnext, float4 *g32);
 // stage 0: evaluate only (writes Rout); stages 1..4: residual + SSP-RK stage.
-// q32next (nullable) receives the FP32 shadow of the new q.
+// q32next (nullable) receives the FP32 shadow of the new q.  lds_budget =
+// bytes of LDS a workgroup may stage its tile image in (tiles with larger
+// images read from memory).
 hipError_t launch_flux(hipStream_t st, const DevCloud &c, const FlowParams &fp, int stage,
-                       const double2 *q, const double2 *g, const double2 *qmm, double *U,
-                       double *Un, double *dt, double2 *qnext, double *Rout, double *partial,
+                       int lds_budget, const double2 *q, const double2 *g, const double2 *qmm,
+                       double *U, double *Un, double *dt, double2 *qnext, double *Rout,
                        float4 *q32next, int *err);
 // mixed precision: reconstruction, limiter and split fluxes in FP32 from the
 // shadows q32, g32, qmm32; weights, residual sums and the update in FP64.
 hipError_t launch_flux_mixed(hipStream_t st, const DevCloud &c, const FlowParams &fp, int stage,
-                             const double2 *q, const float4 *q32, const float4 *g32,
-                             const float4 *qmm32, double *U, double *Un, double *dt,
-                             double2 *qnext, float4 *q32next, double *Rout, double *partial,
+                             int lds_budget, const double2 *q, const float4 *q32,
+                             const float4 *g32, const float4 *qmm32, double *U, double *Un,
+                             double *dt, double2 *qnext, float4 *q32next, double *Rout,
                              int *err);
-hipError_t launch_resnorm(hipStream_t st, int nblk, const double *partial, double inv_nupd,
-                          double *out);
+// warm start: de-standardisation of the network's (rho, u1, u2, p) and the
+// lower bound of rho and p relative to the freestream
+struct WarmScale {
+    float mean[4], std[4];
+    double floor;
+};
+hipError_t launch_warm_state(hipStream_t st, int n, const int *perm, const uint8_t *kind,
+                             const double2 *nrm, const int *case_of, const double *uinf,
+                             const float *Y, const WarmScale &sc, double gamma, double *U);
+hipError_t launch_select_state(hipStream_t st, int n, const int *case_of, const uint8_t *sel,
+                               const double *Uw, double *U);
+hipError_t launch_wall_distance(hipStream_t st, int n, const double2 *xy, const int *case_of,
+                                const int *wall_lo, const int *wall, double *d);
+// residual norms per case into history row *ctr (then *ctr += 1)
+hipError_t launch_resnorm(hipStream_t st, const double *R, int n, int nchunk, const int *chunk_beg,
+                          double *part, int ncase, const int *chunk_ptr, const double *inv_nupd,
+                          int *ctr, int cap, double *hist);
 hipError_t launch_forces(hipStream_t st, int nw, const int *wall, const double2 *xy,
                          const double2 *nrm, const double *U, int n, double gamma, double pinf,
                          double *scratch, double *out);

@@ -19,6 +19,7 @@
 //   split-flux derivatives   eqs. (12)-(14)
 //   iteration                sec. 3 Algorithm 1
 #include "qlskum_internal.h"
+#include "qlskum_erfc.h"
 
 #include <climits>
 #include <cmath>
@@ -60,11 +61,13 @@ __device__ __forceinline__ void store4(double2 *a, int p, const double v[4]) {
     a[2 * p + 1] = make_double2(v[2], v[3]);
 }
 
-__device__ __forceinline__ void store8(double2 *a, int p, const double v[8]) {
-    a[4 * p] = make_double2(v[0], v[1]);
-    a[4 * p + 1] = make_double2(v[2], v[3]);
-    a[4 * p + 2] = make_double2(v[4], v[5]);
-    a[4 * p + 3] = make_double2(v[6], v[7]);
+// Sum over the kFluxLanes lanes that serve one point, in the fixed order
+// (l0 + l1) + (l2 + l3); every lane of the group receives the same value
+// (floating-point addition is commutative).
+__device__ __forceinline__ double lane_group_sum(double v) {
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    return v;
 }
 
 __device__ __forceinline__ float4 to_f4(const double v[4]) {
@@ -118,6 +121,7 @@ __global__ void __launch_bounds__(kBlock) k_setup(int n, const double2 *__restri
                                                   const int *__restrict__ ptr,
                                                   const int *__restrict__ idx, uint8_t *flag,
                                                   int classify, double *__restrict__ lsw,
+                                                  double *__restrict__ lsi,
                                                   double *__restrict__ dmin, int *err) {
 #pragma clang fp contract(off)
     const int p = point_id();
@@ -161,6 +165,9 @@ __global__ void __launch_bounds__(kBlock) k_setup(int n, const double2 *__restri
     dmin[p] = sqrt(dm2);
     const double D = a * c - b * b;
     bool bad = !(D > 1e-12 * (a + c) * (a + c)) || (k1 - k0) < 2;
+    lsi[3 * p] = c / D;
+    lsi[3 * p + 1] = b / D;
+    lsi[3 * p + 2] = a / D;
     const uint8_t kd = kind[p];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -181,9 +188,9 @@ __global__ void __launch_bounds__(kBlock) k_setup(int n, const double2 *__restri
 
 hipError_t launch_setup(hipStream_t st, int n, const double2 *xy, const double2 *nrm,
                         const uint8_t *kind, const int *ptr, const int *idx, uint8_t *flag,
-                        int classify, double *lsw, double *dmin, int *err) {
+                        int classify, double *lsw, double *lsi, double *dmin, int *err) {
     hipLaunchKernelGGL(k_setup, dim3(num_blocks(n)), dim3(kBlock), 0, st, n, xy, nrm, kind, ptr,
-                       idx, flag, classify, lsw, dmin, err);
+                       idx, flag, classify, lsw, lsi, dmin, err);
     return hipGetLastError();
 }
 
@@ -199,20 +206,116 @@ __device__ __forceinline__ void wall_project(double U[4], double2 N) {
 
 __global__ void __launch_bounds__(kBlock) k_freestream(int n, const double2 *__restrict__ nrm,
                                                        const uint8_t *__restrict__ kind,
-                                                       double u0, double u1, double u2, double u3,
+                                                       const int *__restrict__ case_of,
+                                                       const double *__restrict__ uinf,
                                                        double *__restrict__ U) {
     const int p = point_id();
     if (p >= n) return;
-    double v[4] = {u0, u1, u2, u3};
+    const double *u = uinf + 4 * case_of[p];
+    double v[4] = {u[0], u[1], u[2], u[3]};
     if (kind[p] == kWall) wall_project(v, nrm[p]);
 #pragma unroll
     for (int c = 0; c < 4; ++c) U[(size_t)c * n + p] = v[c];
 }
 
 hipError_t launch_freestream(hipStream_t st, int n, const double2 *nrm, const uint8_t *kind,
-                             const double *Uinf, double *U) {
+                             const int *case_of, const double *uinf, double *U) {
     hipLaunchKernelGGL(k_freestream, dim3(num_blocks(n)), dim3(kBlock), 0, st, n, nrm, kind,
-                       Uinf[0], Uinf[1], Uinf[2], Uinf[3], U);
+                       case_of, uinf, U);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Warm start: a state from the network's primitive fields, and the choice
+// between it and the freestream per case.
+// ---------------------------------------------------------------------------
+// Y[caller point][4] = standardised (rho, u1, u2, p); prim = mean + std * Y,
+// rho and p held at or above `floor` times their freestream values; outer
+// points keep the freestream (their Dirichlet condition); wall points are
+// projected.
+__global__ void __launch_bounds__(kBlock) k_warm_state(int n, const int *__restrict__ perm,
+                                                       const uint8_t *__restrict__ kind,
+                                                       const double2 *__restrict__ nrm,
+                                                       const int *__restrict__ case_of,
+                                                       const double *__restrict__ uinf,
+                                                       const float *__restrict__ Y, WarmScale sc,
+                                                       double gamma, double *__restrict__ U) {
+    const int p = point_id();
+    if (p >= n) return;
+    const double *u = uinf + 4 * case_of[p];
+    double v[4] = {u[0], u[1], u[2], u[3]};
+    if (kind[p] != kOuter) {
+        const float *y = Y + 4 * (size_t)perm[p];
+        double pr[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pr[c] = (double)sc.mean[c] + (double)sc.std[c] * (double)y[c];
+        const double pinf = 1.0 / gamma;  // rho_inf = 1, c_inf = 1
+        const double rho = fmax(pr[0], sc.floor);
+        const double pp = fmax(pr[3], sc.floor * pinf);
+        v[0] = rho;
+        v[1] = rho * pr[1];
+        v[2] = rho * pr[2];
+        v[3] = pp / (gamma - 1.0) + 0.5 * rho * (pr[1] * pr[1] + pr[2] * pr[2]);
+        if (!(isfinite(v[1]) && isfinite(v[2]) && isfinite(v[3]))) {
+            v[0] = u[0]; v[1] = u[1]; v[2] = u[2]; v[3] = u[3];
+        }
+        if (kind[p] == kWall) wall_project(v, nrm[p]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) U[(size_t)c * n + p] = v[c];
+}
+
+hipError_t launch_warm_state(hipStream_t st, int n, const int *perm, const uint8_t *kind,
+                             const double2 *nrm, const int *case_of, const double *uinf,
+                             const float *Y, const WarmScale &sc, double gamma, double *U) {
+    hipLaunchKernelGGL(k_warm_state, dim3(num_blocks(n)), dim3(kBlock), 0, st, n, perm, kind, nrm,
+                       case_of, uinf, Y, sc, gamma, U);
+    return hipGetLastError();
+}
+
+// U <- Uw at the points of the cases with sel[case] != 0
+__global__ void __launch_bounds__(kBlock) k_select_state(int n, const int *__restrict__ case_of,
+                                                         const uint8_t *__restrict__ sel,
+                                                         const double *__restrict__ Uw,
+                                                         double *__restrict__ U) {
+    const int p = point_id();
+    if (p >= n || !sel[case_of[p]]) return;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) U[(size_t)c * n + p] = Uw[(size_t)c * n + p];
+}
+
+hipError_t launch_select_state(hipStream_t st, int n, const int *case_of, const uint8_t *sel,
+                               const double *Uw, double *U) {
+    hipLaunchKernelGGL(k_select_state, dim3(num_blocks(n)), dim3(kBlock), 0, st, n, case_of, sel,
+                       Uw, U);
+    return hipGetLastError();
+}
+
+// Distance of every point to the nearest wall point of its case (brute
+// force over the case's wall list; walls hold a few hundred points).  A case
+// without wall points gets +inf.
+__global__ void __launch_bounds__(kBlock) k_wall_distance(int n, const double2 *__restrict__ xy,
+                                                          const int *__restrict__ case_of,
+                                                          const int *__restrict__ wall_lo,
+                                                          const int *__restrict__ wall,
+                                                          double *__restrict__ d) {
+    const int p = point_id();
+    if (p >= n) return;
+    const int c = case_of[p];
+    const double2 P = xy[p];
+    double best = INFINITY;
+    for (int k = wall_lo[c]; k < wall_lo[c + 1]; ++k) {
+        const double2 W = xy[wall[k]];
+        const double dx = W.x - P.x, dy = W.y - P.y;
+        best = fmin(best, dx * dx + dy * dy);
+    }
+    d[p] = sqrt(best);
+}
+
+hipError_t launch_wall_distance(hipStream_t st, int n, const double2 *xy, const int *case_of,
+                                const int *wall_lo, const int *wall, double *d) {
+    hipLaunchKernelGGL(k_wall_distance, dim3(num_blocks(n)), dim3(kBlock), 0, st, n, xy, case_of,
+                       wall_lo, wall, d);
     return hipGetLastError();
 }
 
@@ -290,323 +393,261 @@ hipError_t launch_prep(hipStream_t st, const DevCloud &c, const FlowParams &fp, 
 }
 
 // ---------------------------------------------------------------------------
-// q-derivatives, first pass: full-stencil least squares of dq_i = q_i - q_p
-// (eq. (11)); also the componentwise max / min of q over the point and its
-// stencil (bounds of the limited reconstruction).
+// q-derivatives, LDS-tiled with the flux sweep's tiles and lane layout: a
+// workgroup owns kFluxTile consecutive points, stages the records its
+// entries gather (its own points and its halo) in LDS, and serves each point
+// with kFluxLanes lanes that walk every kFluxLanes-th entry; the lane sums
+// are combined in a fixed order (lane_group_sum), so each point's sums have
+// one order whichever path (LDS or memory) a tile takes.  The full-stencil
+// least-squares matrix is inverted once at set-up (lsi = (Syy, Sxy, Sxx)/Det).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_grad0(DevCloud cl, const double2 *__restrict__ q,
+namespace {
+
+__device__ __forceinline__ double lane_group_max(double v) {
+    v = fmax(v, __shfl_xor(v, 1, 64));
+    return fmax(v, __shfl_xor(v, 2, 64));
+}
+
+__device__ __forceinline__ double lane_group_min(double v) {
+    v = fmin(v, __shfl_xor(v, 1, 64));
+    return fmin(v, __shfl_xor(v, 2, 64));
+}
+
+// tile set-up shared by the tiled sweeps: image size ns and whether it is
+// staged (cap = slots that fit the LDS allocation of the launch)
+struct TileInfo {
+    int base, nown, h0, ns;
+    bool in_lds;
+};
+
+__device__ __forceinline__ TileInfo tile_info(const DevCloud &cl, int t, int cap) {
+    TileInfo ti;
+    ti.base = t * kFluxTile;
+    ti.nown = min(kFluxTile, cl.n - ti.base);
+    ti.h0 = 0;
+    ti.ns = 0;
+    if (cl.fhalo_ptr) {
+        ti.h0 = cl.fhalo_ptr[t];
+        ti.ns = kFluxTile + cl.fhalo_ptr[t + 1] - ti.h0;
+    }
+    ti.in_lds = cl.fhalo_ptr != nullptr && ti.ns <= cap;
+    return ti;
+}
+
+// point held by image slot s (own slots beyond the cloud's end return -1)
+__device__ __forceinline__ int slot_point(const DevCloud &cl, const TileInfo &ti, int s) {
+    if (s < kFluxTile) return s < ti.nown ? ti.base + s : -1;
+    return cl.fhalo_idx[ti.h0 + s - kFluxTile];
+}
+
+}  // namespace
+
+// first pass: full-stencil least squares of dq_i = q_i - q_p (eq. (11)), and
+// the componentwise max / min of q over the point and its stencil (bounds of
+// the limited reconstruction).  Slot record (double2): q 0..1, position 2.
+__global__ void __launch_bounds__(kBlock) k_grad0(DevCloud cl, int cap,
+                                                  const double2 *__restrict__ q,
                                                   double2 *__restrict__ g,
                                                   double2 *__restrict__ qmm, int want_bounds,
                                                   Shadow sh) {
-    const int p = point_id();
-    if (p >= cl.n) return;
-    const double2 P = cl.xy[p];
-    double qp[4];
-    load4(q, p, qp);
-    double a = 0.0, b = 0.0, c = 0.0;
-    double sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
-    double mx[4] = {qp[0], qp[1], qp[2], qp[3]}, mn[4] = {qp[0], qp[1], qp[2], qp[3]};
-    const int k1 = cl.ptr[p + 1];
-    for (int k = cl.ptr[p]; k < k1; ++k) {
-        const int i = cl.idx[k];
-        const double2 Q = cl.xy[i];
-        const double dx = Q.x - P.x, dy = Q.y - P.y;
-        double qi[4];
-        load4(q, i, qi);
-        a += dx * dx;
-        b += dx * dy;
-        c += dy * dy;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const double dq = qi[r] - qp[r];
-            sx[r] += dx * dq;
-            sy[r] += dy * dq;
-            mx[r] = fmax(mx[r], qi[r]);
-            mn[r] = fmin(mn[r], qi[r]);
+    constexpr int kRec = 3;
+    extern __shared__ double2 lds[];
+    const int t = logical_block();
+    if (cl.tile_active && !cl.tile_active[t]) return;
+    const TileInfo ti = tile_info(cl, t, cap);
+    if (ti.in_lds) {
+        for (int e = threadIdx.x; e < 2 * ti.ns; e += kBlock) {
+            const int pt = slot_point(cl, ti, e >> 1);
+            if (pt >= 0) lds[kRec * (e >> 1) + (e & 1)] = q[2 * pt + (e & 1)];
+        }
+        for (int s = threadIdx.x; s < ti.ns; s += kBlock) {
+            const int pt = slot_point(cl, ti, s);
+            if (pt >= 0) lds[kRec * s + 2] = cl.xy[pt];
         }
     }
-    const double D = a * c - b * b;
+    __syncthreads();
+    const int j = threadIdx.x / kFluxLanes, sub = threadIdx.x % kFluxLanes;
+    const int p = ti.base + j;
+    double sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
+    double mx[4] = {0, 0, 0, 0}, mn[4] = {0, 0, 0, 0};
+    if (j < ti.nown) {
+        double qp[4];
+        double2 P;
+        if (ti.in_lds) {
+            const double2 *r = lds + kRec * j;
+            qp[0] = r[0].x; qp[1] = r[0].y; qp[2] = r[1].x; qp[3] = r[1].y;
+            P = r[2];
+        } else {
+            load4(q, p, qp);
+            P = cl.xy[p];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) mx[r] = mn[r] = qp[r];
+        const int k1 = cl.ptr[p + 1];
+        for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
+            double qi[4];
+            double2 Q;
+            if (ti.in_lds) {
+                const double2 *r = lds + kRec * (int)cl.flidx[k];
+                qi[0] = r[0].x; qi[1] = r[0].y; qi[2] = r[1].x; qi[3] = r[1].y;
+                Q = r[2];
+            } else {
+                const int i = cl.idx[k];
+                load4(q, i, qi);
+                Q = cl.xy[i];
+            }
+            const double dx = Q.x - P.x, dy = Q.y - P.y;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double dq = qi[r] - qp[r];
+                sx[r] = fma(dx, dq, sx[r]);
+                sy[r] = fma(dy, dq, sy[r]);
+                mx[r] = fmax(mx[r], qi[r]);
+                mn[r] = fmin(mn[r], qi[r]);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        sx[r] = lane_group_sum(sx[r]);
+        sy[r] = lane_group_sum(sy[r]);
+        mx[r] = lane_group_max(mx[r]);
+        mn[r] = lane_group_min(mn[r]);
+    }
+    if (j >= ti.nown) return;
+    const double L0 = cl.lsi[3 * p], L1 = cl.lsi[3 * p + 1], L2 = cl.lsi[3 * p + 2];
     double gv[8];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        gv[r] = (c * sx[r] - b * sy[r]) / D;
-        gv[4 + r] = (a * sy[r] - b * sx[r]) / D;
+        gv[r] = fma(L0, sx[r], -(L1 * sy[r]));
+        gv[4 + r] = fma(L2, sy[r], -(L1 * sx[r]));
     }
-    store8(g, p, gv);
-    if (sh.g32) {
-        sh.g32[2 * p] = to_f4(gv);
-        sh.g32[2 * p + 1] = to_f4(gv + 4);
-    }
+    // each of the point's lanes stores one 16-byte part
+    g[4 * p + sub] = make_double2(gv[2 * sub], gv[2 * sub + 1]);
+    if (sh.g32 && sub < 2) sh.g32[2 * p + sub] = to_f4(gv + 4 * sub);
     if (want_bounds) {
-        double bv[8] = {mx[0], mx[1], mx[2], mx[3], mn[0], mn[1], mn[2], mn[3]};
-        store8(qmm, p, bv);
-        if (sh.qmm32) {
-            sh.qmm32[2 * p] = to_f4(bv);
-            sh.qmm32[2 * p + 1] = to_f4(bv + 4);
-        }
+        const double bv[8] = {mx[0], mx[1], mx[2], mx[3], mn[0], mn[1], mn[2], mn[3]};
+        qmm[4 * p + sub] = make_double2(bv[2 * sub], bv[2 * sub + 1]);
+        if (sh.qmm32 && sub < 2) sh.qmm32[2 * p + sub] = to_f4(bv + 4 * sub);
     }
 }
 
-hipError_t launch_grad0(hipStream_t st, const DevCloud &c, const double2 *q, double2 *g,
-                        double2 *qmm, int want_bounds, Shadow sh) {
-    hipLaunchKernelGGL(k_grad0, dim3(num_blocks(c.n)), dim3(kBlock), 0, st, c, q, g, qmm,
-                       want_bounds, sh);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// q-derivatives, one inner iteration (eq. (29)): least squares of
-//   dq~_i = dq_i - 1/2 [dx (q_x,i - q_x,p) + dy (q_y,i - q_y,p)]
-// from the previous iterate (Jacobi: read gprev, write gnext).
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_gradk(DevCloud cl, const double2 *__restrict__ q,
+// one inner iteration (eq. (29)).  The least squares is linear in its data:
+//   g^k = LS(dq_i) - 1/2 LS(d.(g^{k-1}_i - g^{k-1}_p)) = g0 - 1/2 LS(...)
+// so only the previous iterate is gathered (Jacobi: read gprev, write gnext).
+// Slot record (double2): g 0..3, position 4.
+__global__ void __launch_bounds__(kBlock) k_gradk(DevCloud cl, int cap,
+                                                  const double2 *__restrict__ g0,
                                                   const double2 *__restrict__ gprev,
                                                   double2 *__restrict__ gnext,
                                                   float4 *__restrict__ g32) {
-    const int p = point_id();
-    if (p >= cl.n) return;
-    const double2 P = cl.xy[p];
-    double qp[4], gp[8];
-    load4(q, p, qp);
-    load8(gprev, p, gp);
-    double a = 0.0, b = 0.0, c = 0.0;
-    double sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
-    const int k1 = cl.ptr[p + 1];
-    for (int k = cl.ptr[p]; k < k1; ++k) {
-        const int i = cl.idx[k];
-        const double2 Q = cl.xy[i];
-        const double dx = Q.x - P.x, dy = Q.y - P.y;
-        double qi[4], gi[8];
-        load4(q, i, qi);
-        load8(gprev, i, gi);
-        a += dx * dx;
-        b += dx * dy;
-        c += dy * dy;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const double dq = (qi[r] - qp[r]) -
-                              0.5 * (dx * (gi[r] - gp[r]) + dy * (gi[4 + r] - gp[4 + r]));
-            sx[r] += dx * dq;
-            sy[r] += dy * dq;
-        }
-    }
-    const double D = a * c - b * b;
-    double gv[8];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        gv[r] = (c * sx[r] - b * sy[r]) / D;
-        gv[4 + r] = (a * sy[r] - b * sx[r]) / D;
-    }
-    store8(gnext, p, gv);
-    if (g32) {
-        g32[2 * p] = to_f4(gv);
-        g32[2 * p + 1] = to_f4(gv + 4);
-    }
-}
-
-hipError_t launch_gradk(hipStream_t st, const DevCloud &c, const double2 *q, const double2 *gprev,
-                        double2 *gnext, float4 *g32) {
-    hipLaunchKernelGGL(k_gradk, dim3(num_blocks(c.n)), dim3(kBlock), 0, st, c, q, gprev, gnext,
-                       g32);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// LDS-tiled q-derivatives.  A workgroup owns a tile of kBlock consecutive
-// points (a compact patch in Hilbert order); it first copies the records of
-// its points and of their neighbours outside the tile (the halo) into LDS,
-// then every lane walks its neighbour list through 16-bit slot indices.
-// Each record is read from memory once per tile instead of once per use.
-// ---------------------------------------------------------------------------
-// Tiles whose image exceeds the budget read their neighbours straight from
-// memory (a branch that is uniform across the workgroup).
-constexpr int kLdsBudget = 64 * 1024;  // bytes of LDS per workgroup at most
-constexpr int kCap0 = kLdsBudget / 48;  // slots of the first-pass image
-constexpr int kCapK = kLdsBudget / 80;  // slots of the inner-iteration image
-
-bool lds_fits_grad0(const DevCloud &c) { return c.max_slots < (1 << 30); }
-bool lds_fits_gradk(const DevCloud &c) { return c.max_slots < (1 << 30); }
-
-// first pass: slot record = (q0,q1) (q2,q3) (x,y)
-__global__ void __launch_bounds__(kBlock) k_grad0_lds(DevCloud cl, const double2 *__restrict__ q,
-                                                      double2 *__restrict__ g,
-                                                      double2 *__restrict__ qmm,
-                                                      int want_bounds, Shadow sh) {
+    constexpr int kRec = 5;
     extern __shared__ double2 lds[];
-    const int n = cl.n;
     const int t = logical_block();
-    const int base = t * kBlock;
-    const int h0 = cl.halo_ptr[t], nh = cl.halo_ptr[t + 1] - h0;
-    const int nown = min(kBlock, n - base);
-    const bool in_lds = kBlock + nh <= kCap0;
-    if (in_lds) {
-        for (int s = threadIdx.x; s < kBlock + nh; s += kBlock) {
-            int pt;
-            if (s < kBlock) {
-                if (s >= nown) continue;
-                pt = base + s;
-            } else {
-                pt = cl.halo_idx[h0 + s - kBlock];
-            }
-            lds[3 * s] = q[2 * pt];
-            lds[3 * s + 1] = q[2 * pt + 1];
-            lds[3 * s + 2] = cl.xy[pt];
+    if (cl.tile_active && !cl.tile_active[t]) return;
+    const TileInfo ti = tile_info(cl, t, cap);
+    if (ti.in_lds) {
+        for (int e = threadIdx.x; e < 4 * ti.ns; e += kBlock) {
+            const int pt = slot_point(cl, ti, e >> 2);
+            if (pt >= 0) lds[kRec * (e >> 2) + (e & 3)] = gprev[4 * pt + (e & 3)];
+        }
+        for (int s = threadIdx.x; s < ti.ns; s += kBlock) {
+            const int pt = slot_point(cl, ti, s);
+            if (pt >= 0) lds[kRec * s + 4] = cl.xy[pt];
         }
     }
     __syncthreads();
-    const int j = threadIdx.x;
-    if (j >= nown) return;
-    const int p = base + j;
-    const double2 q01 = q[2 * p], q23 = q[2 * p + 1], P = cl.xy[p];
-    const double qp[4] = {q01.x, q01.y, q23.x, q23.y};
-    double a = 0.0, b = 0.0, c = 0.0;
+    const int j = threadIdx.x / kFluxLanes, sub = threadIdx.x % kFluxLanes;
+    const int p = ti.base + j;
     double sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
-    double mx[4] = {qp[0], qp[1], qp[2], qp[3]}, mn[4] = {qp[0], qp[1], qp[2], qp[3]};
-    const int k1 = cl.ptr[p + 1];
-    for (int k = cl.ptr[p]; k < k1; ++k) {
-        double2 a01, a23, Q;
-        if (in_lds) {
-            const int li = cl.lidx[k];
-            a01 = lds[3 * li];
-            a23 = lds[3 * li + 1];
-            Q = lds[3 * li + 2];
-        } else {
-            const int i = cl.idx[k];
-            a01 = q[2 * i];
-            a23 = q[2 * i + 1];
-            Q = cl.xy[i];
-        }
-        const double qi[4] = {a01.x, a01.y, a23.x, a23.y};
-        const double dx = Q.x - P.x, dy = Q.y - P.y;
-        a += dx * dx;
-        b += dx * dy;
-        c += dy * dy;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const double dq = qi[r] - qp[r];
-            sx[r] += dx * dq;
-            sy[r] += dy * dq;
-            mx[r] = fmax(mx[r], qi[r]);
-            mn[r] = fmin(mn[r], qi[r]);
-        }
-    }
-    const double D = a * c - b * b;
-    double gv[8];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        gv[r] = (c * sx[r] - b * sy[r]) / D;
-        gv[4 + r] = (a * sy[r] - b * sx[r]) / D;
-    }
-    store8(g, p, gv);
-    if (sh.g32) {
-        sh.g32[2 * p] = to_f4(gv);
-        sh.g32[2 * p + 1] = to_f4(gv + 4);
-    }
-    if (want_bounds) {
-        double bv[8] = {mx[0], mx[1], mx[2], mx[3], mn[0], mn[1], mn[2], mn[3]};
-        store8(qmm, p, bv);
-        if (sh.qmm32) {
-            sh.qmm32[2 * p] = to_f4(bv);
-            sh.qmm32[2 * p + 1] = to_f4(bv + 4);
-        }
-    }
-}
-
-hipError_t launch_grad0_lds(hipStream_t st, const DevCloud &c, const double2 *q, double2 *g,
-                            double2 *qmm, int want_bounds, Shadow sh) {
-    const size_t shmem = (size_t)min(c.max_slots, kCap0) * 48;
-    hipLaunchKernelGGL(k_grad0_lds, dim3(num_blocks(c.n)), dim3(kBlock), shmem, st, c, q, g, qmm,
-                       want_bounds, sh);
-    return hipGetLastError();
-}
-
-// inner iteration: the least squares of eq. (29) is linear in its data, so
-//   g^k = LS(dq_i) - 1/2 LS(d.(g^{k-1}_i - g^{k-1}_p)) = g0 - 1/2 LS(...)
-// and only the previous iterate is gathered.  slot record = g (4 x double2)
-// and (x, y).
-__global__ void __launch_bounds__(kBlock) k_gradk_lds(DevCloud cl, const double2 *__restrict__ g0,
-                                                      const double2 *__restrict__ gprev,
-                                                      double2 *__restrict__ gnext,
-                                                      float4 *__restrict__ g32) {
-    extern __shared__ double2 lds[];
-    const int n = cl.n;
-    const int t = logical_block();
-    const int base = t * kBlock;
-    const int h0 = cl.halo_ptr[t], nh = cl.halo_ptr[t + 1] - h0;
-    const int nown = min(kBlock, n - base);
-    const bool in_lds = kBlock + nh <= kCapK;
-    if (in_lds) {
-        for (int s = threadIdx.x; s < kBlock + nh; s += kBlock) {
-            int pt;
-            if (s < kBlock) {
-                if (s >= nown) continue;
-                pt = base + s;
-            } else {
-                pt = cl.halo_idx[h0 + s - kBlock];
-            }
-#pragma unroll
-            for (int m = 0; m < 4; ++m) lds[5 * s + m] = gprev[4 * pt + m];
-            lds[5 * s + 4] = cl.xy[pt];
-        }
-    }
-    __syncthreads();
-    const int j = threadIdx.x;
-    if (j >= nown) return;
-    const int p = base + j;
-    double gp[8];
-    load8(gprev, p, gp);
-    const double2 P = cl.xy[p];
-    double a = 0.0, b = 0.0, c = 0.0;
-    double sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
-    const int k1 = cl.ptr[p + 1];
-    for (int k = cl.ptr[p]; k < k1; ++k) {
-        double gi[8];
-        double2 Q;
-        if (in_lds) {
-            const int li = cl.lidx[k];
+    if (j < ti.nown) {
+        double gp[8];
+        double2 P;
+        if (ti.in_lds) {
+            const double2 *r = lds + kRec * j;
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                const double2 v = lds[5 * li + m];
-                gi[2 * m] = v.x;
-                gi[2 * m + 1] = v.y;
+                gp[2 * m] = r[m].x;
+                gp[2 * m + 1] = r[m].y;
             }
-            Q = lds[5 * li + 4];
+            P = r[4];
         } else {
-            const int i = cl.idx[k];
-            load8(gprev, i, gi);
-            Q = cl.xy[i];
+            load8(gprev, p, gp);
+            P = cl.xy[p];
         }
-        const double dx = Q.x - P.x, dy = Q.y - P.y;
-        a += dx * dx;
-        b += dx * dy;
-        c += dy * dy;
+        const int k1 = cl.ptr[p + 1];
+        for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
+            double gi[8];
+            double2 Q;
+            if (ti.in_lds) {
+                const double2 *r = lds + kRec * (int)cl.flidx[k];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const double f = dx * (gi[r] - gp[r]) + dy * (gi[4 + r] - gp[4 + r]);
-            sx[r] += dx * f;
-            sy[r] += dy * f;
+                for (int m = 0; m < 4; ++m) {
+                    gi[2 * m] = r[m].x;
+                    gi[2 * m + 1] = r[m].y;
+                }
+                Q = r[4];
+            } else {
+                const int i = cl.idx[k];
+                load8(gprev, i, gi);
+                Q = cl.xy[i];
+            }
+            const double dx = Q.x - P.x, dy = Q.y - P.y;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double f = fma(dx, gi[r] - gp[r], dy * (gi[4 + r] - gp[4 + r]));
+                sx[r] = fma(dx, f, sx[r]);
+                sy[r] = fma(dy, f, sy[r]);
+            }
         }
     }
-    const double D = a * c - b * b;
-    double gz[8], gv[8];
-    load8(g0, p, gz);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        gv[r] = gz[r] - 0.5 * ((c * sx[r] - b * sy[r]) / D);
-        gv[4 + r] = gz[4 + r] - 0.5 * ((a * sy[r] - b * sx[r]) / D);
+        sx[r] = lane_group_sum(sx[r]);
+        sy[r] = lane_group_sum(sy[r]);
     }
-    store8(gnext, p, gv);
+    if (j >= ti.nown) return;
+    const double L0 = cl.lsi[3 * p], L1 = cl.lsi[3 * p + 1], L2 = cl.lsi[3 * p + 2];
+    // lane sub produces components 2 sub, 2 sub + 1 of (q_x[0..3], q_y[0..3])
+    const double2 z = g0[4 * p + sub];
+    double v[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const int c = 2 * sub + m, r = c & 3;
+        const double ls = (c < 4) ? fma(L0, sx[r], -(L1 * sy[r])) : fma(L2, sy[r], -(L1 * sx[r]));
+        v[m] = fma(-0.5, ls, m == 0 ? z.x : z.y);
+    }
+    gnext[4 * p + sub] = make_double2(v[0], v[1]);
     if (g32) {
-        g32[2 * p] = to_f4(gv);
-        g32[2 * p + 1] = to_f4(gv + 4);
+        // the FP32 shadow packs (q_x[0..3]) and (q_y[0..3]): lanes 0,1 and 2,3
+        // hold halves of one float4, combined through a shuffle of partner lanes
+        const double o0 = __shfl_xor(v[0], 1, 64), o1 = __shfl_xor(v[1], 1, 64);
+        if ((sub & 1) == 0)
+            g32[2 * p + (sub >> 1)] =
+                make_float4((float)v[0], (float)v[1], (float)o0, (float)o1);
     }
 }
 
-hipError_t launch_gradk_lds(hipStream_t st, const DevCloud &c, const double2 *g0,
-                            const double2 *gprev, double2 *gnext, float4 *g32) {
-    const size_t shmem = (size_t)min(c.max_slots, kCapK) * 80;
-    hipLaunchKernelGGL(k_gradk_lds, dim3(num_blocks(c.n)), dim3(kBlock), shmem, st, c, g0, gprev,
-                       gnext, g32);
+static int lds_cap(const DevCloud &c, int budget, int rec) {
+    if (!c.fhalo_ptr) return 0;
+    return min(c.fmax_slots, max(budget / rec, 0));
+}
+
+hipError_t launch_grad0(hipStream_t st, const DevCloud &c, int lds_budget, const double2 *q,
+                        double2 *g, double2 *qmm, int want_bounds, Shadow sh) {
+    const int rec = 3 * (int)sizeof(double2);
+    const int cap = lds_cap(c, lds_budget, rec);
+    hipLaunchKernelGGL(k_grad0, dim3(num_flux_tiles(c.n)), dim3(kBlock), (size_t)cap * rec, st, c,
+                       cap, q, g, qmm, want_bounds, sh);
+    return hipGetLastError();
+}
+
+hipError_t launch_gradk(hipStream_t st, const DevCloud &c, int lds_budget, const double2 *g0,
+                        const double2 *gprev, double2 *gnext, float4 *g32) {
+    const int rec = 5 * (int)sizeof(double2);
+    const int cap = lds_cap(c, lds_budget, rec);
+    hipLaunchKernelGGL(k_gradk, dim3(num_flux_tiles(c.n)), dim3(kBlock), (size_t)cap * rec, st, c,
+                       cap, g0, gprev, gnext, g32);
     return hipGetLastError();
 }
 
@@ -652,7 +693,8 @@ __device__ __forceinline__ bool q_to_prim(const double qt[4], const FlowParams &
 
 // Kinetic split flux along the unit direction e; sg = +1 for G+, -1 for G-.
 // Half-range moments of the Maxwellian: with S = u_e sqrt(beta),
-// A = erfc(-sg S)/2 and B = exp(-S^2)/(2 sqrt(pi beta)),
+// A = erfc(-sg S)/2 and B = exp(-S^2)/(2 sqrt(pi beta)) (one exponential
+// serves both, see qlskum_erfc.h),
 //   G = [rho(u_e A + sg B), rho u (u_e A + sg B) + p A e,
 //        (p + rho e) u_e A + sg (p/2 + rho e) B].
 __device__ __forceinline__ void split_flux(const Prim &s, double ex, double ey, double sg,
@@ -661,8 +703,9 @@ __device__ __forceinline__ void split_flux(const Prim &s, double ex, double ey, 
     constexpr double kHalfRsqrtPi = 0.28209479177387814347;  // 1 / (2 sqrt(pi))
     const double ue = fma(s.u1, ex, s.u2 * ey);
     const double S = ue * s.sqb;
-    const double A = 0.5 * erfc(-sg * S);
-    const double B = (exp(-(S * S)) * kHalfRsqrtPi) * s.isqb;
+    const double E = gauss(S);
+    const double A = half_erfc(-sg * S, E);
+    const double B = (E * kHalfRsqrtPi) * s.isqb;
     const double sB = sg * B;
     const double mass = s.rho * fma(ue, A, sB);
     const double pA = s.p * A;
@@ -672,12 +715,16 @@ __device__ __forceinline__ void split_flux(const Prim &s, double ex, double ey, 
     G[3] = fma((s.p + s.rhoe) * ue, A, (fma(0.5, s.p, s.rhoe)) * sB);
 }
 
-// Venkatakrishnan limiter value for the increment delta of one component.
+// Venkatakrishnan limiter value for the increment delta of one component:
+//   phi = (D^2 + eps^2 + 2 delta D) / (D^2 + 2 delta^2 + delta D + eps^2)
+// with D = qmax - q (delta > 0) or qmin - q.
 __device__ __forceinline__ double venkat(double delta, double q, double qmx, double qmn,
                                          double eps2) {
+#pragma clang fp contract(off)
     const double D = (delta > 0.0) ? (qmx - q) : (qmn - q);
-    const double num = (D * D + eps2) + 2.0 * delta * D;
-    const double den = D * D + 2.0 * delta * delta + delta * D + eps2;
+    const double a = fma(D, D, eps2);
+    const double num = fma(2.0 * delta, D, a);
+    const double den = fma(delta, D, fma(2.0 * delta, delta, a));
     return (den == 0.0) ? 1.0 : num / den;
 }
 
@@ -687,16 +734,132 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-}  // namespace
+// Contribution of one neighbour entry (split flags f, offset (dx, dy) from p
+// to i) to the residual of p: the modified states q~_i and q~_p of eq. (28)
+// (limited when LIMITER), their split fluxes, and w_b (G(q~_i) - G(q~_p))
+// added for each split stencil b the entry belongs to (one s half and one n
+// half at most).  w holds p's eight least-squares factors (see k_setup).
+// Written with explicit fma and no implicit contraction: a point's residual
+// depends only on its data and on the order of its entries, never on the code
+// path that gathered them.  Returns false when a modified state has no
+// Maxwellian.
+template <bool LIMITER, int POW>
+__device__ __forceinline__ bool flux_entry(uint8_t f, double dx, double dy, double2 N,
+                                           const double qi[4], const double gi[8],
+                                           const double bi[8], const double qp[4],
+                                           const double gp[8], const double bp[8],
+                                           const double w[8], const FlowParams &fp,
+                                           double R[4]) {
+#pragma clang fp contract(off)
+    const double tx = N.y, ty = -N.x;
+    const double ds = fma(dx, tx, dy * ty);
+    const double dn = fma(dx, N.x, dy * N.y);
+    double qti[4], qt0[4];
+    if (LIMITER) {
+        const double e = fp.venkat_k * sqrt(fma(dx, dx, dy * dy));
+        const double eps2 = (e * e) * e;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double di = -0.5 * fma(dx, gi[r], dy * gi[4 + r]);
+            const double d0 = -0.5 * fma(dx, gp[r], dy * gp[4 + r]);
+            qti[r] = fma(venkat(di, qi[r], bi[r], bi[4 + r], eps2), di, qi[r]);
+            qt0[r] = fma(venkat(d0, qp[r], bp[r], bp[4 + r], eps2), d0, qp[r]);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            qti[r] = fma(-0.5, fma(dx, gi[r], dy * gi[4 + r]), qi[r]);
+            qt0[r] = fma(-0.5, fma(dx, gp[r], dy * gp[4 + r]), qp[r]);
+        }
+    }
+    Prim si, s0;
+    bool ok = q_to_prim<POW>(qti, fp, si);
+    ok &= q_to_prim<POW>(qt0, fp, s0);
+    if (f & (kSPlus | kSMinus)) {
+        const bool plus = (f & kSPlus) != 0;
+        const double sg = plus ? 1.0 : -1.0;
+        const double wt = fma(ds, plus ? w[0] : w[2], -(dn * (plus ? w[1] : w[3])));
+        double Gi[4], G0[4];
+        split_flux(si, tx, ty, sg, Gi);
+        split_flux(s0, tx, ty, sg, G0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) R[r] = fma(wt, Gi[r] - G0[r], R[r]);
+    }
+    if (f & (kNPlus | kNMinus)) {
+        const bool plus = (f & kNPlus) != 0;
+        const double sg = plus ? 1.0 : -1.0;
+        const double wt = fma(dn, plus ? w[4] : w[6], -(ds * (plus ? w[5] : w[7])));
+        double Gi[4], G0[4];
+        split_flux(si, N.x, N.y, sg, Gi);
+        split_flux(s0, N.x, N.y, sg, G0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) R[r] = fma(wt, Gi[r] - G0[r], R[r]);
+    }
+    return ok;
+}
 
-// stage 0: evaluate R only.  stage 1..4: SSP-RK(4,3) stage with L = -R:
+// SSP-RK(4,3) stage of point p with L = -R:
 //   U1 = Un + dt/2 L(Un); U2 = U1 + dt/2 L(U1);
 //   U3 = 2/3 Un + 1/3 (U2 + dt/2 L(U2)); U4 = U3 + dt/2 L(U3);
-// then the wall projection, q of the new state into qnext, and at stage 4
-// the next iteration's Un and time step.  Stage 1 also writes one partial
-// sum of R_c^2 per workgroup (residual norm).
+// then the wall projection, q of the new state into qnext (and its FP32
+// shadow), and at stage 4 the next iteration's Un and time step.
+__device__ __forceinline__ void rk_update(const DevCloud &cl, const FlowParams &fp, int stage,
+                                          int p, uint8_t kd, double2 N, const double R[4],
+                                          double *U, double *Un, double *dt, double2 *qnext,
+                                          float4 *q32next, int *err) {
+    const int n = cl.n;
+    const double h = 0.5 * dt[p];
+    double v[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const double u = U[(size_t)c * n + p];
+        if (stage == 3)
+            v[c] = (2.0 / 3.0) * Un[(size_t)c * n + p] + (1.0 / 3.0) * (u - h * R[c]);
+        else
+            v[c] = u - h * R[c];
+    }
+    if (kd == kWall) wall_project(v, N);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) U[(size_t)c * n + p] = v[c];
+    double qq[4];
+    const int e = cons_to_q(v, fp, qq);
+    if (e != kErrNone) {
+        report(err, p, e);
+        qq[0] = qq[1] = qq[2] = 0.0;
+        qq[3] = -1.0;
+    }
+    store4(qnext, p, qq);
+    if (q32next) q32next[p] = to_f4(qq);
+    if (stage == 4) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Un[(size_t)c * n + p] = v[c];
+        dt[p] = local_dt(v, cl.dmin[p], fp);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Flux residual + Runge-Kutta stage, LDS-tiled.
+//
+// A workgroup owns a tile of kFluxTile consecutive points (a compact patch in
+// Hilbert order) and serves each point with kFluxLanes lanes: lane l walks the
+// point's neighbour entries l, l + kFluxLanes, ... and the partial sums are
+// combined by lane_group_sum, so every point's residual is summed in one fixed
+// order.  The records that the entries gather (q, q-derivatives, limiter
+// bounds, position) of the tile's points and of its halo are first copied
+// into LDS; each is read from memory once per tile instead of once per use.
+// A tile whose image exceeds the capacity `cap` (slots) reads straight from
+// memory (a branch uniform across the workgroup), with the same arithmetic.
+//
+// stage 0: evaluate R only (into Rout).  stage 1..4: residual + rk_update;
+// stage 1 also writes R to Rout for the residual norm.  Outer and frozen
+// points are held (q copied to qnext) and carry R = 0.
+// ---------------------------------------------------------------------------
+int num_flux_tiles(int n) { return (n + kFluxTile - 1) / kFluxTile; }
+
 template <bool LIMITER, int POW>
-__global__ void __launch_bounds__(kBlock) k_flux(DevCloud cl, FlowParams fp, int stage,
+__global__ void __launch_bounds__(kBlock) k_flux(DevCloud cl, FlowParams fp, int stage, int cap,
                                                  const double2 *__restrict__ q,
                                                  const double2 *__restrict__ g,
                                                  const double2 *__restrict__ qmm,
@@ -704,156 +867,146 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevCloud cl, FlowParams fp, int
                                                  double *__restrict__ dt,
                                                  double2 *__restrict__ qnext,
                                                  double *__restrict__ Rout,
-                                                 double *__restrict__ partial,
                                                  float4 *__restrict__ q32next, int *err) {
+    // slot record (double2): q 0..1, g 2..5, bounds 6..9, position last
+    constexpr int kRec = LIMITER ? 11 : 7;
+    extern __shared__ double2 lds[];
     const int n = cl.n;
-    const int p = point_id();
+    const int t = logical_block();
+    if (cl.tile_active && !cl.tile_active[t]) return;
+    const int base = t * kFluxTile;
+    const int nown = min(kFluxTile, n - base);
+    int h0 = 0, ns = 0;
+    if (cl.fhalo_ptr) {
+        h0 = cl.fhalo_ptr[t];
+        ns = kFluxTile + cl.fhalo_ptr[t + 1] - h0;
+    }
+    const bool in_lds = cl.fhalo_ptr != nullptr && ns <= cap;
+    if (in_lds) {
+        auto slot_point = [&](int s) {
+            return s < kFluxTile ? base + s : cl.fhalo_idx[h0 + s - kFluxTile];
+        };
+        for (int e = threadIdx.x; e < 2 * ns; e += kBlock) {
+            const int s = e >> 1;
+            if (s >= nown && s < kFluxTile) continue;
+            lds[kRec * s + (e & 1)] = q[2 * slot_point(s) + (e & 1)];
+        }
+        for (int e = threadIdx.x; e < 4 * ns; e += kBlock) {
+            const int s = e >> 2;
+            if (s >= nown && s < kFluxTile) continue;
+            const int pt = slot_point(s);
+            lds[kRec * s + 2 + (e & 3)] = g[4 * pt + (e & 3)];
+            if (LIMITER) lds[kRec * s + 6 + (e & 3)] = qmm[4 * pt + (e & 3)];
+        }
+        for (int s = threadIdx.x; s < ns; s += kBlock) {
+            if (s >= nown && s < kFluxTile) continue;
+            lds[kRec * s + kRec - 1] = cl.xy[slot_point(s)];
+        }
+    }
+    __syncthreads();
+    const int j = threadIdx.x / kFluxLanes, sub = threadIdx.x % kFluxLanes;
+    const int p = base + j;
     double R[4] = {0.0, 0.0, 0.0, 0.0};
-    bool updated = false;
-    if (p < n) {
-        const uint8_t kd = cl.kind[p];
-        double qp[4];
-        load4(q, p, qp);
-        if (kd == kOuter) {
-            if (stage > 0) {  // held at the far-field state
-                store4(qnext, p, qp);
-                if (q32next) q32next[p] = to_f4(qp);
-            }
-            if (Rout) {
+    uint8_t kd = kOuter;
+    bool live = false;
+    if (j < nown) {
+        kd = cl.kind[p];
+        const bool frozen = cl.case_active && !cl.case_active[cl.case_of[p]];
+        live = kd != kOuter && !frozen;
+    }
+    double2 N = make_double2(0.0, 0.0);
+    if (live) {
+        N = cl.nrm[p];
+        double qp[4], gp[8], bp[8], w[8];
+        double2 P;
+        if (in_lds) {
+            const double2 *r = lds + kRec * j;
+            qp[0] = r[0].x; qp[1] = r[0].y; qp[2] = r[1].x; qp[3] = r[1].y;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) Rout[(size_t)r * n + p] = 0.0;
+            for (int m = 0; m < 4; ++m) {
+                gp[2 * m] = r[2 + m].x;
+                gp[2 * m + 1] = r[2 + m].y;
+                if (LIMITER) {
+                    bp[2 * m] = r[6 + m].x;
+                    bp[2 * m + 1] = r[6 + m].y;
+                }
             }
+            P = r[kRec - 1];
         } else {
-            updated = true;
-            const double2 P = cl.xy[p], N = cl.nrm[p];
-            const double tx = N.y, ty = -N.x;
-            double gp[8], bp[8], w[8];
+            load4(q, p, qp);
             load8(g, p, gp);
             if (LIMITER) load8(qmm, p, bp);
+            P = cl.xy[p];
+        }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) w[j] = cl.lsw[8 * p + j];
-            const uint8_t fmask = (kd == kWall) ? uint8_t(~kNPlus) : uint8_t(0xff);
-            const int k1 = cl.ptr[p + 1];
-            bool ok = true;
-            for (int k = cl.ptr[p]; k < k1; ++k) {
-                const uint8_t f = cl.flag[k] & fmask;
-                if (f == 0) continue;
+        for (int m = 0; m < 8; ++m) w[m] = cl.lsw[8 * p + m];
+        const uint8_t fmask = (kd == kWall) ? uint8_t(~kNPlus) : uint8_t(0xff);
+        const int k1 = cl.ptr[p + 1];
+        bool ok = true;
+        for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
+            const uint8_t f = cl.flag[k] & fmask;
+            if (f == 0) continue;
+            double qi[4], gi[8], bi[8];
+            double2 Q;
+            if (in_lds) {
+                const double2 *r = lds + kRec * (int)cl.flidx[k];
+                qi[0] = r[0].x; qi[1] = r[0].y; qi[2] = r[1].x; qi[3] = r[1].y;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    gi[2 * m] = r[2 + m].x;
+                    gi[2 * m + 1] = r[2 + m].y;
+                    if (LIMITER) {
+                        bi[2 * m] = r[6 + m].x;
+                        bi[2 * m + 1] = r[6 + m].y;
+                    }
+                }
+                Q = r[kRec - 1];
+            } else {
                 const int i = cl.idx[k];
-                const double2 Q = cl.xy[i];
-                const double dx = Q.x - P.x, dy = Q.y - P.y;
-                const double ds = dx * tx + dy * ty;
-                const double dn = dx * N.x + dy * N.y;
-                double qi[4], gi[8], qti[4], qt0[4];
                 load4(q, i, qi);
                 load8(g, i, gi);
-                if (LIMITER) {
-                    double bi[8];
-                    load8(qmm, i, bi);
-                    const double e = fp.venkat_k * sqrt(dx * dx + dy * dy);
-                    const double eps2 = e * e * e;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const double di = -0.5 * (dx * gi[r] + dy * gi[4 + r]);
-                        const double d0 = -0.5 * (dx * gp[r] + dy * gp[4 + r]);
-                        qti[r] = qi[r] + venkat(di, qi[r], bi[r], bi[4 + r], eps2) * di;
-                        qt0[r] = qp[r] + venkat(d0, qp[r], bp[r], bp[4 + r], eps2) * d0;
-                    }
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        qti[r] = qi[r] - 0.5 * (dx * gi[r] + dy * gi[4 + r]);
-                        qt0[r] = qp[r] - 0.5 * (dx * gp[r] + dy * gp[4 + r]);
-                    }
-                }
-                Prim si, s0;
-                ok &= q_to_prim<POW>(qti, fp, si);
-                ok &= q_to_prim<POW>(qt0, fp, s0);
-                if (f & (kSPlus | kSMinus)) {
-                    const bool plus = (f & kSPlus) != 0;
-                    const double sg = plus ? 1.0 : -1.0;
-                    const double wa = plus ? w[0] : w[2], wb = plus ? w[1] : w[3];
-                    const double wt = ds * wa - dn * wb;
-                    double Gi[4], G0[4];
-                    split_flux(si, tx, ty, sg, Gi);
-                    split_flux(s0, tx, ty, sg, G0);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) R[r] += wt * (Gi[r] - G0[r]);
-                }
-                if (f & (kNPlus | kNMinus)) {
-                    const bool plus = (f & kNPlus) != 0;
-                    const double sg = plus ? 1.0 : -1.0;
-                    const double wa = plus ? w[4] : w[6], wb = plus ? w[5] : w[7];
-                    const double wt = dn * wa - ds * wb;
-                    double Gi[4], G0[4];
-                    split_flux(si, N.x, N.y, sg, Gi);
-                    split_flux(s0, N.x, N.y, sg, G0);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) R[r] += wt * (Gi[r] - G0[r]);
-                }
+                if (LIMITER) load8(qmm, i, bi);
+                Q = cl.xy[i];
             }
-            if (!ok) report(err, p, kErrPositivity);
-            if (Rout) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) Rout[(size_t)r * n + p] = R[r];
-            }
-            if (stage > 0) {
-                const double h = 0.5 * dt[p];
-                double v[4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const double u = U[(size_t)c * n + p];
-                    if (stage == 3)
-                        v[c] = (2.0 / 3.0) * Un[(size_t)c * n + p] + (1.0 / 3.0) * (u - h * R[c]);
-                    else
-                        v[c] = u - h * R[c];
-                }
-                if (kd == kWall) wall_project(v, N);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) U[(size_t)c * n + p] = v[c];
-                double qq[4];
-                const int e = cons_to_q(v, fp, qq);
-                if (e != kErrNone) {
-                    report(err, p, e);
-                    qq[0] = qq[1] = qq[2] = 0.0;
-                    qq[3] = -1.0;
-                }
-                store4(qnext, p, qq);
-                if (q32next) q32next[p] = to_f4(qq);
-                if (stage == 4) {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) Un[(size_t)c * n + p] = v[c];
-                    dt[p] = local_dt(v, cl.dmin[p], fp);
-                }
-            }
+            ok &= flux_entry<LIMITER, POW>(f, Q.x - P.x, Q.y - P.y, N, qi, gi, bi, qp, gp, bp, w,
+                                           fp, R);
         }
+        if (!ok) report(err, p, kErrPositivity);
     }
-    if (partial != nullptr) {
-        // deterministic per-workgroup sums of R_c^2 over the updated points
-        __shared__ double red[kBlock / 64][4];
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const double s = wave_sum(updated ? R[c] * R[c] : 0.0);
-            if (lane == 0) red[wv][c] = s;
+    for (int r = 0; r < 4; ++r) R[r] = lane_group_sum(R[r]);
+    if (j >= nown || sub != 0) return;
+    if (!live) {
+        if (stage > 0) {
+            double qv[4];
+            load4(q, p, qv);
+            store4(qnext, p, qv);
+            if (q32next) q32next[p] = to_f4(qv);
         }
-        __syncthreads();
-        if (threadIdx.x < 4) {
-            double s = 0.0;
+        if (Rout) {
 #pragma unroll
-            for (int j = 0; j < kBlock / 64; ++j) s += red[j][threadIdx.x];
-            partial[4 * logical_block() + threadIdx.x] = s;
+            for (int r = 0; r < 4; ++r) Rout[(size_t)r * n + p] = 0.0;
         }
+        return;
     }
+    if (Rout) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Rout[(size_t)r * n + p] = R[r];
+    }
+    if (stage > 0) rk_update(cl, fp, stage, p, kd, N, R, U, Un, dt, qnext, q32next, err);
 }
 
 hipError_t launch_flux(hipStream_t st, const DevCloud &c, const FlowParams &fp, int stage,
-                       const double2 *q, const double2 *g, const double2 *qmm, double *U,
-                       double *Un, double *dt, double2 *qnext, double *Rout, double *partial,
+                       int lds_budget, const double2 *q, const double2 *g, const double2 *qmm,
+                       double *U, double *Un, double *dt, double2 *qnext, double *Rout,
                        float4 *q32next, int *err) {
-    const dim3 grid(num_blocks(c.n)), block(kBlock);
-#define QL_FLUX_LAUNCH(LIM, POW)                                                               \
-    hipLaunchKernelGGL((k_flux<LIM, POW>), grid, block, 0, st, c, fp, stage, q, g, qmm, U, Un, \
-                       dt, qnext, Rout, partial, q32next, err)
+    const int rec = (fp.limiter ? 11 : 7) * (int)sizeof(double2);
+    const int cap = lds_cap(c, lds_budget, rec);
+    const size_t shmem = (size_t)cap * rec;
+    const dim3 grid(num_flux_tiles(c.n)), block(kBlock);
+#define QL_FLUX_LAUNCH(LIM, POW)                                                          \
+    hipLaunchKernelGGL((k_flux<LIM, POW>), grid, block, shmem, st, c, fp, stage, cap, q, g, \
+                       qmm, U, Un, dt, qnext, Rout, q32next, err)
     if (fp.sqrt_pow == 5) {  // gamma = 1.4
         if (fp.limiter) QL_FLUX_LAUNCH(true, 5);
         else QL_FLUX_LAUNCH(false, 5);
@@ -870,7 +1023,9 @@ hipError_t launch_flux(hipStream_t st, const DevCloud &c, const FlowParams &fp, 
 // (eq. (28)), the limiter and the split fluxes run in FP32 from the FP32
 // shadows of q, its derivatives and its bounds, using the hardware FP32
 // exp / sqrt / reciprocal; the geometry, the least-squares weights, the
-// residual sums and the state update stay FP64.
+// residual sums and the state update stay FP64.  Same tiling and lane
+// layout as k_flux; the LDS image holds the FP32 records (16-byte q, 32-byte
+// derivatives and bounds) and the FP64 positions.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -908,8 +1063,9 @@ __device__ __forceinline__ void split_flux_f(const PrimF &s, float ex, float ey,
     constexpr float kHalfRsqrtPi = 0.28209479177387814347f;
     const float ue = fmaf(s.u1, ex, s.u2 * ey);
     const float S = ue * s.sqb;
-    const float A = 0.5f * erfcf(-sg * S);
-    const float B = (__expf(-(S * S)) * kHalfRsqrtPi) * s.isqb;
+    const float E = __expf(-(S * S));
+    const float A = half_erfc_f(-sg * S, E);
+    const float B = (E * kHalfRsqrtPi) * s.isqb;
     const float sB = sg * B;
     const float mass = s.rho * fmaf(ue, A, sB);
     const float pA = s.p * A;
@@ -920,9 +1076,11 @@ __device__ __forceinline__ void split_flux_f(const PrimF &s, float ex, float ey,
 }
 
 __device__ __forceinline__ float venkat_f(float delta, float q, float qmx, float qmn, float eps2) {
+#pragma clang fp contract(off)
     const float D = (delta > 0.0f) ? (qmx - q) : (qmn - q);
-    const float num = (D * D + eps2) + 2.0f * delta * D;
-    const float den = D * D + 2.0f * delta * delta + delta * D + eps2;
+    const float a = fmaf(D, D, eps2);
+    const float num = fmaf(2.0f * delta, D, a);
+    const float den = fmaf(delta, D, fmaf(2.0f * delta, delta, a));
     return (den == 0.0f) ? 1.0f : num / den;
 }
 
@@ -930,40 +1088,135 @@ __device__ __forceinline__ void unpack(const float4 a, float *v) {
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
 }
 
+// FP32 counterpart of flux_entry; the weights and sums stay FP64.
+template <bool LIMITER, int POW>
+__device__ __forceinline__ bool flux_entry_f(uint8_t f, double dx, double dy, double2 N,
+                                             const float qi[4], const float gi[8],
+                                             const float bi[8], const float qp[4],
+                                             const float gp[8], const float bp[8],
+                                             const double w[8], float gm1inv, float vk,
+                                             double R[4]) {
+#pragma clang fp contract(off)
+    const double tx = N.y, ty = -N.x;
+    const double ds = fma(dx, tx, dy * ty);
+    const double dn = fma(dx, N.x, dy * N.y);
+    const float dxf = (float)dx, dyf = (float)dy;
+    float qti[4], qt0[4];
+    if (LIMITER) {
+        const float e = vk * sqrtf(fmaf(dxf, dxf, dyf * dyf));
+        const float eps2 = (e * e) * e;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float di = -0.5f * fmaf(dxf, gi[r], dyf * gi[4 + r]);
+            const float d0 = -0.5f * fmaf(dxf, gp[r], dyf * gp[4 + r]);
+            qti[r] = fmaf(venkat_f(di, qi[r], bi[r], bi[4 + r], eps2), di, qi[r]);
+            qt0[r] = fmaf(venkat_f(d0, qp[r], bp[r], bp[4 + r], eps2), d0, qp[r]);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            qti[r] = fmaf(-0.5f, fmaf(dxf, gi[r], dyf * gi[4 + r]), qi[r]);
+            qt0[r] = fmaf(-0.5f, fmaf(dxf, gp[r], dyf * gp[4 + r]), qp[r]);
+        }
+    }
+    PrimF si, s0;
+    bool ok = q_to_prim_f<POW>(qti, gm1inv, si);
+    ok &= q_to_prim_f<POW>(qt0, gm1inv, s0);
+    if (f & (kSPlus | kSMinus)) {
+        const bool plus = (f & kSPlus) != 0;
+        const float sg = plus ? 1.0f : -1.0f;
+        const double wt = fma(ds, plus ? w[0] : w[2], -(dn * (plus ? w[1] : w[3])));
+        float Gi[4], G0[4];
+        split_flux_f(si, (float)tx, (float)ty, sg, Gi);
+        split_flux_f(s0, (float)tx, (float)ty, sg, G0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) R[r] = fma(wt, (double)(Gi[r] - G0[r]), R[r]);
+    }
+    if (f & (kNPlus | kNMinus)) {
+        const bool plus = (f & kNPlus) != 0;
+        const float sg = plus ? 1.0f : -1.0f;
+        const double wt = fma(dn, plus ? w[4] : w[6], -(ds * (plus ? w[5] : w[7])));
+        float Gi[4], G0[4];
+        split_flux_f(si, (float)N.x, (float)N.y, sg, Gi);
+        split_flux_f(s0, (float)N.x, (float)N.y, sg, G0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) R[r] = fma(wt, (double)(Gi[r] - G0[r]), R[r]);
+    }
+    return ok;
+}
+
 }  // namespace
 
 template <bool LIMITER, int POW>
 __global__ void __launch_bounds__(kBlock) k_flux_mixed(
-    DevCloud cl, FlowParams fp, int stage, const double2 *__restrict__ q,
+    DevCloud cl, FlowParams fp, int stage, int cap, const double2 *__restrict__ q,
     const float4 *__restrict__ q32, const float4 *__restrict__ g32,
     const float4 *__restrict__ qmm32, double *__restrict__ U, double *__restrict__ Un,
     double *__restrict__ dt, double2 *__restrict__ qnext, float4 *__restrict__ q32next,
-    double *__restrict__ Rout, double *__restrict__ partial, int *err) {
+    double *__restrict__ Rout, int *err) {
+    // slot record (float4): q 0, g 1..2, bounds 3..4; positions after cap records
+    constexpr int kRec = LIMITER ? 5 : 3;
+    extern __shared__ float4 ldsf[];
+    double2 *lxy = reinterpret_cast<double2 *>(ldsf + (size_t)kRec * cap);
     const int n = cl.n;
-    const int p = point_id();
+    const int t = logical_block();
+    if (cl.tile_active && !cl.tile_active[t]) return;
+    const int base = t * kFluxTile;
+    const int nown = min(kFluxTile, n - base);
+    int h0 = 0, ns = 0;
+    if (cl.fhalo_ptr) {
+        h0 = cl.fhalo_ptr[t];
+        ns = kFluxTile + cl.fhalo_ptr[t + 1] - h0;
+    }
+    const bool in_lds = cl.fhalo_ptr != nullptr && ns <= cap;
+    if (in_lds) {
+        auto slot_point = [&](int s) {
+            return s < kFluxTile ? base + s : cl.fhalo_idx[h0 + s - kFluxTile];
+        };
+        for (int e = threadIdx.x; e < 2 * ns; e += kBlock) {
+            const int s = e >> 1;
+            if (s >= nown && s < kFluxTile) continue;
+            const int pt = slot_point(s);
+            ldsf[kRec * s + 1 + (e & 1)] = g32[2 * pt + (e & 1)];
+            if (LIMITER) ldsf[kRec * s + 3 + (e & 1)] = qmm32[2 * pt + (e & 1)];
+        }
+        for (int s = threadIdx.x; s < ns; s += kBlock) {
+            if (s >= nown && s < kFluxTile) continue;
+            const int pt = slot_point(s);
+            ldsf[kRec * s] = q32[pt];
+            lxy[s] = cl.xy[pt];
+        }
+    }
+    __syncthreads();
+    const int j = threadIdx.x / kFluxLanes, sub = threadIdx.x % kFluxLanes;
+    const int p = base + j;
     double R[4] = {0.0, 0.0, 0.0, 0.0};
-    bool updated = false;
-    if (p < n) {
-        const uint8_t kd = cl.kind[p];
-        if (kd == kOuter) {
-            if (stage > 0) {
-                double qp[4];
-                load4(q, p, qp);
-                store4(qnext, p, qp);
-                q32next[p] = q32[p];
+    uint8_t kd = kOuter;
+    bool live = false;
+    if (j < nown) {
+        kd = cl.kind[p];
+        const bool frozen = cl.case_active && !cl.case_active[cl.case_of[p]];
+        live = kd != kOuter && !frozen;
+    }
+    double2 N = make_double2(0.0, 0.0);
+    if (live) {
+        const float gm1inv = (float)fp.gm1inv;
+        const float vk = (float)fp.venkat_k;
+        N = cl.nrm[p];
+        float qp[4], gp[8], bp[8];
+        double w[8];
+        double2 P;
+        if (in_lds) {
+            const float4 *r = ldsf + kRec * j;
+            unpack(r[0], qp);
+            unpack(r[1], gp);
+            unpack(r[2], gp + 4);
+            if (LIMITER) {
+                unpack(r[3], bp);
+                unpack(r[4], bp + 4);
             }
-            if (Rout) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) Rout[(size_t)r * n + p] = 0.0;
-            }
+            P = lxy[j];
         } else {
-            updated = true;
-            const float gm1inv = (float)fp.gm1inv;
-            const float vk = (float)fp.venkat_k;
-            const double2 P = cl.xy[p], N = cl.nrm[p];
-            const double tx = N.y, ty = -N.x;
-            const float txf = (float)tx, tyf = (float)ty, nxf = (float)N.x, nyf = (float)N.y;
-            float qp[4], gp[8], bp[8];
             unpack(q32[p], qp);
             unpack(g32[2 * p], gp);
             unpack(g32[2 * p + 1], gp + 4);
@@ -971,132 +1224,80 @@ __global__ void __launch_bounds__(kBlock) k_flux_mixed(
                 unpack(qmm32[2 * p], bp);
                 unpack(qmm32[2 * p + 1], bp + 4);
             }
-            double w[8];
+            P = cl.xy[p];
+        }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) w[j] = cl.lsw[8 * p + j];
-            const uint8_t fmask = (kd == kWall) ? uint8_t(~kNPlus) : uint8_t(0xff);
-            const int k1 = cl.ptr[p + 1];
-            bool ok = true;
-            for (int k = cl.ptr[p]; k < k1; ++k) {
-                const uint8_t f = cl.flag[k] & fmask;
-                if (f == 0) continue;
+        for (int m = 0; m < 8; ++m) w[m] = cl.lsw[8 * p + m];
+        const uint8_t fmask = (kd == kWall) ? uint8_t(~kNPlus) : uint8_t(0xff);
+        const int k1 = cl.ptr[p + 1];
+        bool ok = true;
+        for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
+            const uint8_t f = cl.flag[k] & fmask;
+            if (f == 0) continue;
+            float qi[4], gi[8], bi[8];
+            double2 Q;
+            if (in_lds) {
+                const int s = cl.flidx[k];
+                const float4 *r = ldsf + kRec * s;
+                unpack(r[0], qi);
+                unpack(r[1], gi);
+                unpack(r[2], gi + 4);
+                if (LIMITER) {
+                    unpack(r[3], bi);
+                    unpack(r[4], bi + 4);
+                }
+                Q = lxy[s];
+            } else {
                 const int i = cl.idx[k];
-                const double2 Q = cl.xy[i];
-                const double dx = Q.x - P.x, dy = Q.y - P.y;
-                const double ds = dx * tx + dy * ty;
-                const double dn = dx * N.x + dy * N.y;
-                const float dxf = (float)dx, dyf = (float)dy;
-                float qi[4], gi[8], qti[4], qt0[4];
                 unpack(q32[i], qi);
                 unpack(g32[2 * i], gi);
                 unpack(g32[2 * i + 1], gi + 4);
                 if (LIMITER) {
-                    float bi[8];
                     unpack(qmm32[2 * i], bi);
                     unpack(qmm32[2 * i + 1], bi + 4);
-                    const float e = vk * sqrtf(dxf * dxf + dyf * dyf);
-                    const float eps2 = e * e * e;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const float di = -0.5f * (dxf * gi[r] + dyf * gi[4 + r]);
-                        const float d0 = -0.5f * (dxf * gp[r] + dyf * gp[4 + r]);
-                        qti[r] = qi[r] + venkat_f(di, qi[r], bi[r], bi[4 + r], eps2) * di;
-                        qt0[r] = qp[r] + venkat_f(d0, qp[r], bp[r], bp[4 + r], eps2) * d0;
-                    }
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        qti[r] = qi[r] - 0.5f * (dxf * gi[r] + dyf * gi[4 + r]);
-                        qt0[r] = qp[r] - 0.5f * (dxf * gp[r] + dyf * gp[4 + r]);
-                    }
                 }
-                PrimF si, s0;
-                ok &= q_to_prim_f<POW>(qti, gm1inv, si);
-                ok &= q_to_prim_f<POW>(qt0, gm1inv, s0);
-                if (f & (kSPlus | kSMinus)) {
-                    const bool plus = (f & kSPlus) != 0;
-                    const float sg = plus ? 1.0f : -1.0f;
-                    const double wt = ds * (plus ? w[0] : w[2]) - dn * (plus ? w[1] : w[3]);
-                    float Gi[4], G0[4];
-                    split_flux_f(si, txf, tyf, sg, Gi);
-                    split_flux_f(s0, txf, tyf, sg, G0);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) R[r] += wt * (double)(Gi[r] - G0[r]);
-                }
-                if (f & (kNPlus | kNMinus)) {
-                    const bool plus = (f & kNPlus) != 0;
-                    const float sg = plus ? 1.0f : -1.0f;
-                    const double wt = dn * (plus ? w[4] : w[6]) - ds * (plus ? w[5] : w[7]);
-                    float Gi[4], G0[4];
-                    split_flux_f(si, nxf, nyf, sg, Gi);
-                    split_flux_f(s0, nxf, nyf, sg, G0);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) R[r] += wt * (double)(Gi[r] - G0[r]);
-                }
+                Q = cl.xy[i];
             }
-            if (!ok) report(err, p, kErrPositivity);
-            if (Rout) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) Rout[(size_t)r * n + p] = R[r];
-            }
-            if (stage > 0) {
-                const double h = 0.5 * dt[p];
-                double v[4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const double u = U[(size_t)c * n + p];
-                    if (stage == 3)
-                        v[c] = (2.0 / 3.0) * Un[(size_t)c * n + p] + (1.0 / 3.0) * (u - h * R[c]);
-                    else
-                        v[c] = u - h * R[c];
-                }
-                if (kd == kWall) wall_project(v, N);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) U[(size_t)c * n + p] = v[c];
-                double qq[4];
-                const int e = cons_to_q(v, fp, qq);
-                if (e != kErrNone) {
-                    report(err, p, e);
-                    qq[0] = qq[1] = qq[2] = 0.0;
-                    qq[3] = -1.0;
-                }
-                store4(qnext, p, qq);
-                q32next[p] = to_f4(qq);
-                if (stage == 4) {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) Un[(size_t)c * n + p] = v[c];
-                    dt[p] = local_dt(v, cl.dmin[p], fp);
-                }
-            }
+            ok &= flux_entry_f<LIMITER, POW>(f, Q.x - P.x, Q.y - P.y, N, qi, gi, bi, qp, gp, bp,
+                                             w, gm1inv, vk, R);
         }
+        if (!ok) report(err, p, kErrPositivity);
     }
-    if (partial != nullptr) {
-        __shared__ double red[kBlock / 64][4];
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const double sres = wave_sum(updated ? R[c] * R[c] : 0.0);
-            if (lane == 0) red[wv][c] = sres;
+    for (int r = 0; r < 4; ++r) R[r] = lane_group_sum(R[r]);
+    if (j >= nown || sub != 0) return;
+    if (!live) {
+        if (stage > 0) {
+            double qv[4];
+            load4(q, p, qv);
+            store4(qnext, p, qv);
+            q32next[p] = q32[p];
         }
-        __syncthreads();
-        if (threadIdx.x < 4) {
-            double acc = 0.0;
+        if (Rout) {
 #pragma unroll
-            for (int j = 0; j < kBlock / 64; ++j) acc += red[j][threadIdx.x];
-            partial[4 * logical_block() + threadIdx.x] = acc;
+            for (int r = 0; r < 4; ++r) Rout[(size_t)r * n + p] = 0.0;
         }
+        return;
     }
+    if (Rout) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Rout[(size_t)r * n + p] = R[r];
+    }
+    if (stage > 0) rk_update(cl, fp, stage, p, kd, N, R, U, Un, dt, qnext, q32next, err);
 }
 
 hipError_t launch_flux_mixed(hipStream_t st, const DevCloud &c, const FlowParams &fp, int stage,
-                             const double2 *q, const float4 *q32, const float4 *g32,
-                             const float4 *qmm32, double *U, double *Un, double *dt,
-                             double2 *qnext, float4 *q32next, double *Rout, double *partial,
+                             int lds_budget, const double2 *q, const float4 *q32,
+                             const float4 *g32, const float4 *qmm32, double *U, double *Un,
+                             double *dt, double2 *qnext, float4 *q32next, double *Rout,
                              int *err) {
-    const dim3 grid(num_blocks(c.n)), block(kBlock);
-#define QL_FLUXM_LAUNCH(LIM, POW)                                                             \
-    hipLaunchKernelGGL((k_flux_mixed<LIM, POW>), grid, block, 0, st, c, fp, stage, q, q32, g32, \
-                       qmm32, U, Un, dt, qnext, q32next, Rout, partial, err)
+    const int rec = ((fp.limiter ? 5 : 3) + 1) * (int)sizeof(float4);
+    const int cap = lds_cap(c, lds_budget, rec);
+    const size_t shmem = (size_t)cap * rec;
+    const dim3 grid(num_flux_tiles(c.n)), block(kBlock);
+#define QL_FLUXM_LAUNCH(LIM, POW)                                                     \
+    hipLaunchKernelGGL((k_flux_mixed<LIM, POW>), grid, block, shmem, st, c, fp, stage, \
+                       cap, q, q32, g32, qmm32, U, Un, dt, qnext, q32next, Rout, err)
     if (fp.sqrt_pow == 5) {
         if (fp.limiter) QL_FLUXM_LAUNCH(true, 5);
         else QL_FLUXM_LAUNCH(false, 5);
@@ -1108,20 +1309,30 @@ hipError_t launch_flux_mixed(hipStream_t st, const DevCloud &c, const FlowParams
     return hipGetLastError();
 }
 
-// Residual norm: sqrt(sum of the workgroup partials / number of updated
-// points), reduced in a fixed order.
-__global__ void __launch_bounds__(kBlock) k_resnorm(int nblk, const double *__restrict__ partial,
-                                                    double inv_nupd, double *__restrict__ out) {
+// Residual norms per case, in a fixed summation order.  Points are split into
+// chunks that never straddle a case (chunk ch = [beg[ch], beg[ch+1])); one
+// workgroup sums R_c^2 over a chunk, then one workgroup adds each case's
+// chunk sums and writes sqrt(sum / updated points) into history row
+// (*ctr) and advances *ctr (replays of a captured iteration need no host
+// bookkeeping).  Outer and frozen points carry R = 0.
+__global__ void __launch_bounds__(kBlock) k_res_chunks(const double *__restrict__ R, int n,
+                                                       const int *__restrict__ beg,
+                                                       double *__restrict__ part) {
     __shared__ double red[kBlock / 64][4];
-    double s[4] = {0, 0, 0, 0};
-    for (int j = threadIdx.x; j < nblk; j += kBlock) {
+    const int ch = blockIdx.x;
+    const int b = beg[ch], e = beg[ch + 1];
+    double acc[4] = {0, 0, 0, 0};
+    for (int p = b + threadIdx.x; p < e; p += kBlock) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) s[c] += partial[4 * j + c];
+        for (int c = 0; c < 4; ++c) {
+            const double r = R[(size_t)c * n + p];
+            acc[c] += r * r;
+        }
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        const double t = wave_sum(s[c]);
+        const double t = wave_sum(acc[c]);
         if (lane == 0) red[wv][c] = t;
     }
     __syncthreads();
@@ -1129,20 +1340,54 @@ __global__ void __launch_bounds__(kBlock) k_resnorm(int nblk, const double *__re
         double t = 0.0;
 #pragma unroll
         for (int j = 0; j < kBlock / 64; ++j) t += red[j][threadIdx.x];
-        out[threadIdx.x] = sqrt(t * inv_nupd);
+        part[4 * ch + threadIdx.x] = t;
     }
 }
 
-hipError_t launch_resnorm(hipStream_t st, int nblk, const double *partial, double inv_nupd,
-                          double *out) {
-    hipLaunchKernelGGL(k_resnorm, dim3(1), dim3(kBlock), 0, st, nblk, partial, inv_nupd, out);
+__global__ void __launch_bounds__(kBlock) k_res_cases(int ncase, const int *__restrict__ chunk_ptr,
+                                                      const double *__restrict__ part,
+                                                      const double *__restrict__ inv_nupd,
+                                                      int *ctr, int cap,
+                                                      double *__restrict__ hist) {
+    __shared__ double red[kBlock / 64][4];
+    const int row = *ctr;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int cs = 0; cs < ncase; ++cs) {
+        double acc[4] = {0, 0, 0, 0};
+        for (int j = chunk_ptr[cs] + threadIdx.x; j < chunk_ptr[cs + 1]; j += kBlock) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] += part[4 * j + c];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double t = wave_sum(acc[c]);
+            if (lane == 0) red[wv][c] = t;
+        }
+        __syncthreads();
+        if (threadIdx.x < 4 && row < cap) {
+            double t = 0.0;
+#pragma unroll
+            for (int j = 0; j < kBlock / 64; ++j) t += red[j][threadIdx.x];
+            hist[((size_t)row * ncase + cs) * 4 + threadIdx.x] = sqrt(t * inv_nupd[cs]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *ctr = row + 1;
+}
+
+hipError_t launch_resnorm(hipStream_t st, const double *R, int n, int nchunk, const int *chunk_beg,
+                          double *part, int ncase, const int *chunk_ptr, const double *inv_nupd,
+                          int *ctr, int cap, double *hist) {
+    hipLaunchKernelGGL(k_res_chunks, dim3(nchunk), dim3(kBlock), 0, st, R, n, chunk_beg, part);
+    hipLaunchKernelGGL(k_res_cases, dim3(1), dim3(kBlock), 0, st, ncase, chunk_ptr, part,
+                       inv_nupd, ctr, cap, hist);
     return hipGetLastError();
 }
 
 // Forces from the wall pressure; wall[j] lists the wall points in the
-// caller's order (the surface polygon).  Contributions are computed in
-// parallel, then summed by one thread in polygon order, separately for the
-// upper, lower and on-axis points.
+// caller's order (the surface polygon).  Each thread sums a contiguous run of
+// the polygon in order, then the runs are added in thread order, separately
+// for the upper, lower and on-axis points (a fixed summation order).
 __global__ void __launch_bounds__(kBlock) k_forces(int nw, const int *__restrict__ wall,
                                                    const double2 *__restrict__ xy,
                                                    const double2 *__restrict__ nrm,
@@ -1150,7 +1395,12 @@ __global__ void __launch_bounds__(kBlock) k_forces(int nw, const int *__restrict
                                                    double gamma, double pinf,
                                                    double *__restrict__ f,
                                                    double *__restrict__ out) {
-    for (int j = threadIdx.x; j < nw; j += kBlock) {
+    (void)f;
+    __shared__ double part[kBlock][6];
+    const int per = (nw + kBlock - 1) / kBlock;
+    const int j0 = threadIdx.x * per, j1 = min(nw, j0 + per);
+    double F[6] = {0, 0, 0, 0, 0, 0};
+    for (int j = j0; j < j1; ++j) {
         const int p = wall[j], pn = wall[(j + 1) % nw], pp = wall[(j + nw - 1) % nw];
         const double2 P = xy[p], Pn = xy[pn], Pp = xy[pp];
         const double ds = 0.5 * (sqrt((Pn.x - P.x) * (Pn.x - P.x) + (Pn.y - P.y) * (Pn.y - P.y)) +
@@ -1159,20 +1409,20 @@ __global__ void __launch_bounds__(kBlock) k_forces(int nw, const int *__restrict
         const double u1 = U[(size_t)n + p] / rho, u2 = U[(size_t)2 * n + p] / rho;
         const double pr = (gamma - 1.0) * (U[(size_t)3 * n + p] - 0.5 * rho * (u1 * u1 + u2 * u2));
         const double2 N = nrm[p];
-        f[3 * j] = -(pr - pinf) * N.x * ds;
-        f[3 * j + 1] = -(pr - pinf) * N.y * ds;
-        f[3 * j + 2] = (P.y > 0.0) ? 0.0 : (P.y < 0.0) ? 1.0 : 2.0;
+        const int h = (P.y > 0.0) ? 0 : (P.y < 0.0) ? 1 : 2;
+        F[2 * h] += -(pr - pinf) * N.x * ds;
+        F[2 * h + 1] += -(pr - pinf) * N.y * ds;
     }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) part[threadIdx.x][k] = F[k];
     __syncthreads();
     if (threadIdx.x == 0) {
-        double F[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-        for (int j = 0; j < nw; ++j) {
-            const int h = (int)f[3 * j + 2];
-            F[h][0] += f[3 * j];
-            F[h][1] += f[3 * j + 1];
-        }
-        out[0] = (F[0][0] + F[1][0]) + F[2][0];
-        out[1] = (F[0][1] + F[1][1]) + F[2][1];
+        double T[6] = {0, 0, 0, 0, 0, 0};
+        for (int t = 0; t < kBlock; ++t)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) T[k] += part[t][k];
+        out[0] = (T[0] + T[2]) + T[4];
+        out[1] = (T[1] + T[3]) + T[5];
     }
 }
 

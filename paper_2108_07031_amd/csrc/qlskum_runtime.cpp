@@ -48,10 +48,15 @@ struct ql_solver {
     std::string err;
     ql_params prm{};
 
-    // cloud (library order)
+    // cloud (library order); a cloud is one or more independent cases, each a
+    // contiguous range of points with its own freestream
     int n = 0;
     int64_t nnz = 0;
-    int n_upd = 0;
+    int ncase = 0;
+    std::vector<int> case_lo;        // [ncase+1] first point of each case
+    std::vector<int> case_nupd;      // updated (interior + wall) points per case
+    std::vector<int> wall_lo;        // [ncase+1] offsets into the wall list
+    std::vector<double> case_mach, case_alpha;
     bool has_cloud = false, has_state = false, has_eval = false, has_res = false;
     std::vector<int> perm;       // library point -> caller point
     std::vector<int> inv;        // caller point -> library point
@@ -65,15 +70,27 @@ struct ql_solver {
     double *U = nullptr, *Un = nullptr, *dt = nullptr, *R = nullptr, *tmp = nullptr;
     double2 *q[2] = {nullptr, nullptr}, *g[3] = {nullptr, nullptr, nullptr}, *qmm = nullptr;
     float4 *q32[2] = {nullptr, nullptr}, *g32 = nullptr, *qmm32 = nullptr;  // FP32 shadows
-    int *halo_ptr = nullptr, *halo_idx = nullptr;
-    uint16_t *lidx = nullptr;
-    int max_slots = 0;
-    double *partial = nullptr, *reshist = nullptr, *fscratch = nullptr, *fout = nullptr;
+    double *lsi = nullptr;
+    int *fhalo_ptr = nullptr, *fhalo_idx = nullptr;  // tiles of kFluxTile points
+    uint16_t *flidx = nullptr;
+    int fmax_slots = 0;
+    std::vector<int> fslots;  // image size (records) of every flux tile
+    double *reshist = nullptr, *fscratch = nullptr, *fout = nullptr;
+    int *case_of = nullptr, *chunk_beg = nullptr, *chunk_ptr = nullptr, *ctr = nullptr;
+    uint8_t *case_active = nullptr, *tile_active = nullptr;
+    double *uinf = nullptr, *part = nullptr, *inv_nupd = nullptr;
+    int nchunk = 0;
+    int zero = 0;  // source of the history-row counter reset
     int reshist_cap = 0;
     int *errw = nullptr;
     int err_init[2] = {INT_MAX, 0};  // source of the error-word reset copies
     int qcur = 0, gfin = 0;
-    double last_res[4] = {0, 0, 0, 0};
+    std::vector<double> last_res;  // [ncase][4]
+
+    // one pseudo-time iteration captured as a graph (batched runs)
+    hipGraphExec_t graph = nullptr;
+    int graph_qcur = -1;
+    bool capturing = false;
 
     bool timing = false;
     bool untiled = false;  // QLSKUM_UNTILED=1: gather straight from memory (A/B checks)
@@ -120,10 +137,19 @@ void free_cloud(ql_solver *s) {
     dfree(s->xy); dfree(s->nrm); dfree(s->kind); dfree(s->flag); dfree(s->ptr); dfree(s->idx);
     dfree(s->dperm); dfree(s->wall); dfree(s->lsw); dfree(s->dmin); dfree(s->U); dfree(s->Un);
     dfree(s->dt); dfree(s->R); dfree(s->tmp); dfree(s->q[0]); dfree(s->q[1]); dfree(s->g[0]);
-    dfree(s->g[1]); dfree(s->g[2]); dfree(s->qmm); dfree(s->partial); dfree(s->reshist);
-    dfree(s->fscratch); dfree(s->fout); dfree(s->errw); dfree(s->halo_ptr); dfree(s->halo_idx);
-    dfree(s->lidx); dfree(s->q32[0]); dfree(s->q32[1]); dfree(s->g32); dfree(s->qmm32);
-    s->max_slots = 0;
+    dfree(s->g[1]); dfree(s->g[2]); dfree(s->qmm); dfree(s->reshist);
+    dfree(s->fscratch); dfree(s->fout); dfree(s->errw); dfree(s->lsi);
+    dfree(s->fhalo_ptr); dfree(s->fhalo_idx); dfree(s->flidx);
+    dfree(s->q32[0]); dfree(s->q32[1]); dfree(s->g32); dfree(s->qmm32);
+    dfree(s->case_of); dfree(s->chunk_beg); dfree(s->chunk_ptr); dfree(s->ctr);
+    dfree(s->case_active); dfree(s->tile_active); dfree(s->uinf); dfree(s->part);
+    dfree(s->inv_nupd);
+    if (s->graph) (void)hipGraphExecDestroy(s->graph);
+    s->graph = nullptr;
+    s->graph_qcur = -1;
+    s->fmax_slots = 0;
+    s->fslots.clear();
+    s->ncase = 0;
     s->reshist_cap = 0;
     s->has_cloud = s->has_state = s->has_eval = s->has_res = false;
     s->n = 0;
@@ -149,6 +175,7 @@ uint64_t hilbert_key(uint32_t x, uint32_t y, int order) {
     return d;
 }
 
+// Hilbert order of the n points x[0..n), y[0..n) (indices relative to them).
 std::vector<int> hilbert_order(int n, const double *x, const double *y) {
     double x0 = x[0], x1 = x[0], y0 = y[0], y1 = y[0];
     for (int p = 1; p < n; ++p) {
@@ -171,20 +198,20 @@ std::vector<int> hilbert_order(int n, const double *x, const double *y) {
     return perm;
 }
 
-// Tiles of kBlock consecutive points: the sorted list of each tile's halo
+// Tiles of T consecutive points: the sorted list of each tile's halo
 // (neighbours outside the tile) and every entry's slot in the tile's LDS
-// image.  Returns the largest image (own slots + halo), or INT_MAX when a
-// slot would not fit 16 bits.
-int build_tiles(int n, const std::vector<int> &ptr, const std::vector<int> &idx,
+// image (own point j -> j, halo point h -> T + h).  Returns the largest image
+// (own slots + halo), or INT_MAX when a slot would not fit 16 bits.
+int build_tiles(int n, int T, const std::vector<int> &ptr, const std::vector<int> &idx,
                 std::vector<int> &hptr, std::vector<int> &hidx, std::vector<uint16_t> &lidx) {
-    const int ntile = num_blocks(n);
+    const int ntile = (n + T - 1) / T;
     hptr.assign(ntile + 1, 0);
     hidx.clear();
     lidx.assign(idx.size(), 0);
     std::vector<int> stamp(n, -1), slot(n, 0), h;
     int max_slots = 0;
     for (int t = 0; t < ntile; ++t) {
-        const int base = t * kBlock, end = std::min(n, base + kBlock);
+        const int base = t * T, end = std::min(n, base + T);
         h.clear();
         for (int p = base; p < end; ++p)
             for (int k = ptr[p]; k < ptr[p + 1]; ++k) {
@@ -195,9 +222,9 @@ int build_tiles(int n, const std::vector<int> &ptr, const std::vector<int> &idx,
                 }
             }
         std::sort(h.begin(), h.end());
-        const int slots = kBlock + (int)h.size();
+        const int slots = T + (int)h.size();
         if (slots > 65535) return INT_MAX;
-        for (size_t j = 0; j < h.size(); ++j) slot[h[j]] = kBlock + (int)j;
+        for (size_t j = 0; j < h.size(); ++j) slot[h[j]] = T + (int)j;
         for (int p = base; p < end; ++p)
             for (int k = ptr[p]; k < ptr[p + 1]; ++k) {
                 const int i = idx[k];
@@ -221,10 +248,15 @@ DevCloud dev_cloud(const ql_solver *s) {
     c.flag = s->flag;
     c.lsw = s->lsw;
     c.dmin = s->dmin;
-    c.halo_ptr = s->halo_ptr;
-    c.halo_idx = s->halo_idx;
-    c.lidx = s->lidx;
-    c.max_slots = s->max_slots;
+    c.lsi = s->lsi;
+    const bool ftiles = s->fhalo_ptr && !s->untiled;
+    c.fhalo_ptr = ftiles ? s->fhalo_ptr : nullptr;
+    c.fhalo_idx = ftiles ? s->fhalo_idx : nullptr;
+    c.flidx = ftiles ? s->flidx : nullptr;
+    c.fmax_slots = ftiles ? s->fmax_slots : 0;
+    c.case_of = s->case_of;
+    c.case_active = s->case_active;
+    c.tile_active = s->tile_active;
     return c;
 }
 
@@ -254,6 +286,8 @@ int check_params(ql_solver *s, const ql_params *p) {
     if (p->precision != 0 && p->precision != 1)
         return fail(s, QL_EINVAL, "precision must be 0 (FP64) or 1 (mixed)");
     if (p->reorder != 0 && p->reorder != 1) return fail(s, QL_EINVAL, "reorder must be 0 or 1");
+    if (p->flux_lds < 0 || p->flux_lds > 160 * 1024)
+        return fail(s, QL_EINVAL, "flux_lds must lie in [0, 163840] bytes");
     return QL_OK;
 }
 
@@ -312,13 +346,13 @@ struct Timer {
     int kind;
     hipEvent_t a = nullptr;
     Timer(ql_solver *s_, int k) : s(s_), kind(k) {
-        if (s->timing) {
+        if (s->timing && !s->capturing) {
             a = take_event(s);
             if (a) (void)hipEventRecord(a, s->stream);
         }
     }
     void done() {
-        if (s->timing && a) {
+        if (s->timing && !s->capturing && a) {
             hipEvent_t b = take_event(s);
             if (b) (void)hipEventRecord(b, s->stream);
             s->pending.push_back({kind, a, b});
@@ -326,13 +360,19 @@ struct Timer {
     }
 };
 
+// LDS bytes a q-derivative workgroup stages its tile image in (records of
+// 48 and 80 bytes).  Sized so that the workgroups the kernels' register use
+// allows per CU (6 and 7 of 256 lanes) stay resident in 160 KB of LDS; the
+// rare tiles with larger images read from memory.
+constexpr int kGrad0Lds = 24 * 1024;
+constexpr int kGradkLds = 22 * 1024;
+
 // One stage's q-derivatives: first pass + n_inner Jacobi iterations; leaves
 // the final iterate in g[gfin].
 int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds) {
-    const bool tiled = !s->untiled;
-    const bool lds0 = tiled && lds_fits_grad0(c), ldsk = tiled && lds_fits_gradk(c);
-    // first pass into g[2] when the inner iterations run tiled (they read g0)
-    const int first = (ldsk && s->prm.n_inner > 0) ? 2 : 0;
+    // the first pass goes to g[2] when inner iterations follow (they read it
+    // as g0); the iterates alternate between g[0] and g[1]
+    const int first = s->prm.n_inner > 0 ? 2 : 0;
     // mixed precision: the last pass also writes the FP32 shadow of g, the
     // first pass the FP32 shadow of the bounds
     const bool mixed = s->prm.precision == 1;
@@ -343,12 +383,8 @@ int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds) {
     }
     {
         Timer t(s, 0);
-        if (lds0)
-            HIPCHK(s, launch_grad0_lds(s->stream, c, s->q[s->qcur], s->g[first], s->qmm,
-                                       want_bounds ? 1 : 0, sh));
-        else
-            HIPCHK(s, launch_grad0(s->stream, c, s->q[s->qcur], s->g[first], s->qmm,
-                                   want_bounds ? 1 : 0, sh));
+        HIPCHK(s, launch_grad0(s->stream, c, kGrad0Lds, s->q[s->qcur], s->g[first], s->qmm,
+                               want_bounds ? 1 : 0, sh));
         t.done();
     }
     int cur = first;
@@ -356,10 +392,7 @@ int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds) {
         const int nxt = (cur == 0) ? 1 : 0;
         float4 *g32 = (mixed && k == s->prm.n_inner - 1) ? s->g32 : nullptr;
         Timer t(s, 1);
-        if (ldsk)
-            HIPCHK(s, launch_gradk_lds(s->stream, c, s->g[2], s->g[cur], s->g[nxt], g32));
-        else
-            HIPCHK(s, launch_gradk(s->stream, c, s->q[s->qcur], s->g[cur], s->g[nxt], g32));
+        HIPCHK(s, launch_gradk(s->stream, c, kGradkLds, s->g[2], s->g[cur], s->g[nxt], g32));
         t.done();
         cur = nxt;
     }
@@ -378,18 +411,97 @@ int prep_state(ql_solver *s) {
     return QL_OK;
 }
 
+// LDS bytes a flux workgroup may stage its tile image in.  The defaults keep
+// the workgroups that the kernels' register use allows per CU resident
+// (3 for FP64 with the limiter, 4 otherwise; 160 KB of LDS per CU).
+int flux_lds_budget(const ql_solver *s) {
+    if (s->prm.flux_lds > 0) return s->prm.flux_lds;
+    return (s->prm.precision == 0 && s->prm.limiter) ? 52 * 1024 : 40 * 1024;
+}
+
 // One flux-residual launch (stage 0: evaluate into R; 1..4: RK stage).
-int launch_stage(ql_solver *s, const DevCloud &c, const FlowParams &fp, int stage, double *Rout,
-                 double *partial) {
+int launch_stage(ql_solver *s, const DevCloud &c, const FlowParams &fp, int stage, double *Rout) {
     const int a = s->qcur, b = 1 - s->qcur;
+    const int lds = flux_lds_budget(s);
     if (s->prm.precision == 1)
-        HIPCHK(s, launch_flux_mixed(s->stream, c, fp, stage, s->q[a], s->q32[a], s->g32, s->qmm32,
-                                    s->U, s->Un, s->dt, s->q[b], s->q32[b], Rout, partial,
+        HIPCHK(s, launch_flux_mixed(s->stream, c, fp, stage, lds, s->q[a], s->q32[a], s->g32,
+                                    s->qmm32, s->U, s->Un, s->dt, s->q[b], s->q32[b], Rout,
                                     s->errw));
     else
-        HIPCHK(s, launch_flux(s->stream, c, fp, stage, s->q[a], s->g[s->gfin], s->qmm, s->U,
-                              s->Un, s->dt, s->q[b], Rout, partial, s->q32[b], s->errw));
+        HIPCHK(s, launch_flux(s->stream, c, fp, stage, lds, s->q[a], s->g[s->gfin], s->qmm, s->U,
+                              s->Un, s->dt, s->q[b], Rout, s->q32[b], s->errw));
     return QL_OK;
+}
+
+// Enqueue one pseudo-time iteration: four stages, then the residual norms of
+// stage 1 into history row *ctr.
+int enqueue_iteration(ql_solver *s, const DevCloud &c, const FlowParams &fp, int hist_cap) {
+    for (int rk = 1; rk <= 4; ++rk) {
+        int st = run_gradients(s, c, fp.limiter != 0);
+        if (st) return st;
+        Timer t(s, 2);
+        st = launch_stage(s, c, fp, rk, rk == 1 ? s->R : nullptr);
+        if (st) return st;
+        t.done();
+        s->qcur = 1 - s->qcur;
+    }
+    Timer t(s, 3);
+    HIPCHK(s, launch_resnorm(s->stream, s->R, s->n, s->nchunk, s->chunk_beg, s->part, s->ncase,
+                             s->chunk_ptr, s->inv_nupd, s->ctr, hist_cap, s->reshist));
+    t.done();
+    return QL_OK;
+}
+
+int ensure_history(ql_solver *s, int rows) {
+    const int need = rows * s->ncase;
+    if (need > s->reshist_cap) {
+        dfree(s->reshist);
+        HIPCHK(s, dalloc(&s->reshist, (size_t)4 * need));
+        s->reshist_cap = need;
+        if (s->graph) (void)hipGraphExecDestroy(s->graph);  // the graph holds the old buffer
+        s->graph = nullptr;
+    }
+    return QL_OK;
+}
+
+int reset_counter(ql_solver *s) {
+    HIPCHK(s, hipMemcpyAsync(s->ctr, &s->zero, sizeof(int), hipMemcpyHostToDevice, s->stream));
+    return QL_OK;
+}
+
+// Capture one iteration into s->graph (rows of history: capacity per replay
+// block is reshist_cap / ncase).
+int capture_iteration(ql_solver *s) {
+    if (s->graph && s->graph_qcur == s->qcur) return QL_OK;
+    if (s->graph) (void)hipGraphExecDestroy(s->graph);
+    s->graph = nullptr;
+    const DevCloud c = dev_cloud(s);
+    const FlowParams fp = flow_params(s);
+    const int q0 = s->qcur;
+    HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    s->capturing = true;
+    int st = enqueue_iteration(s, c, fp, s->reshist_cap / s->ncase);
+    s->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s->stream, &g);
+    if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(s, QL_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(&s->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess)
+        return fail(s, QL_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e2));
+    s->qcur = q0;  // capture enqueued nothing; the four stage flips cancel anyway
+    s->graph_qcur = q0;
+    return QL_OK;
+}
+
+void drop_graph(ql_solver *s) {
+    if (s->graph) (void)hipGraphExecDestroy(s->graph);
+    s->graph = nullptr;
+    s->graph_qcur = -1;
 }
 
 int ensure_ready(ql_solver *s, bool need_state) {
@@ -415,6 +527,7 @@ void ql_default_params(ql_params *p) {
     p->venkat_k = 5.0;
     p->precision = 0;
     p->reorder = 1;
+    p->flux_lds = 0;
 }
 
 int ql_create(ql_solver **out, int32_t device, void *hip_stream) {
@@ -470,18 +583,25 @@ int ql_set_params(ql_solver *s, const ql_params *p) {
     int st = check_params(s, p);
     if (st) return st;
     s->prm = *p;
+    drop_graph(s);
     return QL_OK;
 }
 
-int ql_upload_cloud(ql_solver *s, int64_t n64, const double *x, const double *y,
-                    const double *nx, const double *ny, const uint8_t *kind,
-                    const int32_t *nbr_ptr, const int32_t *nbr_idx, const uint8_t *nbr_flag) {
+static int upload_impl(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int64_t n64,
+                       const double *x, const double *y, const double *nx, const double *ny,
+                       const uint8_t *kind, const int32_t *nbr_ptr, const int32_t *nbr_idx,
+                       const uint8_t *nbr_flag, const double *mach, const double *alpha) {
     if (!s) return QL_EINVAL;
     if (s->poisoned) return QL_EDEVICE;
     if (!x || !y || !nx || !ny || !kind || !nbr_ptr || (!nbr_idx && n64 > 0))
         return fail(s, QL_EINVAL, "null array argument");
     if (n64 < 1 || n64 > INT_MAX / 8) return fail(s, QL_EINVAL, "n = %lld out of range", (long long)n64);
     const int n = (int)n64;
+    if (ncase < 1 || ncase > n) return fail(s, QL_EINVAL, "ncase = %d out of range", ncase);
+    if (case_ptr[0] != 0 || case_ptr[ncase] != n64)
+        return fail(s, QL_EINVAL, "case_ptr must start at 0 and end at n");
+    for (int c = 0; c < ncase; ++c)
+        if (case_ptr[c + 1] <= case_ptr[c]) return fail(s, QL_EINVAL, "case %d is empty", c);
     if (nbr_ptr[0] != 0) return fail(s, QL_EINVAL, "nbr_ptr[0] must be 0");
     for (int p = 0; p < n; ++p) {
         if (nbr_ptr[p + 1] < nbr_ptr[p]) return fail(s, QL_EINVAL, "nbr_ptr decreases at point %d", p);
@@ -492,31 +612,48 @@ int ql_upload_cloud(ql_solver *s, int64_t n64, const double *x, const double *y,
         if (!(std::fabs(nn - 1.0) < 1e-8)) return fail(s, QL_EINVAL, "normal of point %d is not unit", p);
     }
     const int64_t nnz = nbr_ptr[n];
-    for (int p = 0; p < n; ++p)
-        for (int k = nbr_ptr[p]; k < nbr_ptr[p + 1]; ++k) {
-            const int i = nbr_idx[k];
-            if (i < 0 || i >= n || i == p)
-                return fail(s, QL_EINVAL, "neighbour entry %d of point %d is out of range or self", k, p);
-            if (nbr_flag && (nbr_flag[k] & ~0x0f))
-                return fail(s, QL_EINVAL, "bad split flag at entry %d", k);
-        }
+    for (int c = 0; c < ncase; ++c) {
+        const int lo = (int)case_ptr[c], hi = (int)case_ptr[c + 1];
+        for (int p = lo; p < hi; ++p)
+            for (int k = nbr_ptr[p]; k < nbr_ptr[p + 1]; ++k) {
+                const int i = nbr_idx[k];
+                if (i < lo || i >= hi || i == p)
+                    return fail(s, QL_EINVAL,
+                                "neighbour entry %d of point %d is out of its case's range or self",
+                                k, p);
+                if (nbr_flag && (nbr_flag[k] & ~0x0f))
+                    return fail(s, QL_EINVAL, "bad split flag at entry %d", k);
+            }
+        if (mach && (!(mach[c] >= 0.0) || !std::isfinite(mach[c])))
+            return fail(s, QL_EINVAL, "bad Mach number of case %d", c);
+        if (alpha && !std::isfinite(alpha[c])) return fail(s, QL_EINVAL, "bad alpha of case %d", c);
+    }
     (void)hipSetDevice(s->device);
     HIPCHK(s, hipStreamSynchronize(s->stream));
     free_cloud(s);
 
-    // point order
-    std::vector<int> perm;
-    if (s->prm.reorder == 1) perm = hilbert_order(n, x, y);
-    else { perm.resize(n); std::iota(perm.begin(), perm.end(), 0); }
+    // point order: each case keeps its range; Hilbert order inside it
+    std::vector<int> perm(n);
+    for (int c = 0; c < ncase; ++c) {
+        const int lo = (int)case_ptr[c], hi = (int)case_ptr[c + 1];
+        if (s->prm.reorder == 1) {
+            const std::vector<int> o = hilbert_order(hi - lo, x + lo, y + lo);
+            for (int j = 0; j < hi - lo; ++j) perm[lo + j] = lo + o[j];
+        } else {
+            for (int j = lo; j < hi; ++j) perm[j] = j;
+        }
+    }
     std::vector<int> inv(n);
     for (int q = 0; q < n; ++q) inv[perm[q]] = q;
 
     // reordered host arrays
     std::vector<double2> hxy(n), hnrm(n);
     std::vector<uint8_t> hkind(n), hflag(nbr_flag ? nnz : 0);
-    std::vector<int> hptr(n + 1), hidx(nnz);
+    std::vector<int> hptr(n + 1), hidx(nnz), hcase(n);
     std::vector<int64_t> eperm(nnz);
     hptr[0] = 0;
+    for (int c = 0; c < ncase; ++c)
+        for (int q = (int)case_ptr[c]; q < (int)case_ptr[c + 1]; ++q) hcase[q] = c;
     for (int q = 0; q < n; ++q) {
         const int p = perm[q];
         hxy[q] = make_double2(x[p], y[p]);
@@ -530,22 +667,44 @@ int ql_upload_cloud(ql_solver *s, int64_t n64, const double *x, const double *y,
         }
         hptr[q + 1] = k;
     }
-    std::vector<int> hwall;
-    int n_upd = 0;
-    for (int p = 0; p < n; ++p) {
-        if (kind[p] == QL_KIND_WALL) hwall.push_back(inv[p]);
-        if (kind[p] != QL_KIND_OUTER) ++n_upd;
+    // per case: walls in the caller's order, updated-point counts, chunks of
+    // the residual reduction (never straddling a case)
+    constexpr int kChunk = 4096;
+    std::vector<int> hwall, wall_lo(ncase + 1, 0), nupd(ncase, 0), cbeg, cptr(ncase + 1, 0);
+    std::vector<double> inv_nupd(ncase);
+    for (int c = 0; c < ncase; ++c) {
+        const int lo = (int)case_ptr[c], hi = (int)case_ptr[c + 1];
+        for (int p = lo; p < hi; ++p) {
+            if (kind[p] == QL_KIND_WALL) hwall.push_back(inv[p]);
+            if (kind[p] != QL_KIND_OUTER) ++nupd[c];
+        }
+        wall_lo[c + 1] = (int)hwall.size();
+        inv_nupd[c] = nupd[c] > 0 ? 1.0 / nupd[c] : 0.0;
+        for (int b = lo; b < hi; b += kChunk) cbeg.push_back(b);
+        cptr[c + 1] = (int)cbeg.size();
     }
-    const int nblk = num_blocks(n);
+    const int nchunk = (int)cbeg.size();
+    cbeg.push_back(n);
+    const int ntile = num_flux_tiles(n);
 
     s->n = n;
     s->nnz = nnz;
-    s->n_upd = n_upd;
+    s->ncase = ncase;
+    s->case_lo.assign(case_ptr, case_ptr + ncase + 1);
+    s->case_nupd = nupd;
+    s->wall_lo = wall_lo;
+    s->case_mach.assign(ncase, s->prm.mach);
+    s->case_alpha.assign(ncase, s->prm.alpha_deg);
+    if (mach) s->case_mach.assign(mach, mach + ncase);
+    if (alpha) s->case_alpha.assign(alpha, alpha + ncase);
+    s->last_res.assign((size_t)4 * ncase, 0.0);
     s->nw = (int)hwall.size();
+    s->nchunk = nchunk;
     HIPCHK(s, dalloc(&s->xy, n)); HIPCHK(s, dalloc(&s->nrm, n)); HIPCHK(s, dalloc(&s->kind, n));
     HIPCHK(s, dalloc(&s->flag, nnz)); HIPCHK(s, dalloc(&s->ptr, n + 1)); HIPCHK(s, dalloc(&s->idx, nnz));
     HIPCHK(s, dalloc(&s->dperm, n)); HIPCHK(s, dalloc(&s->wall, hwall.size()));
     HIPCHK(s, dalloc(&s->lsw, (size_t)8 * n)); HIPCHK(s, dalloc(&s->dmin, n));
+    HIPCHK(s, dalloc(&s->lsi, (size_t)3 * n));
     HIPCHK(s, dalloc(&s->U, (size_t)4 * n)); HIPCHK(s, dalloc(&s->Un, (size_t)4 * n));
     HIPCHK(s, dalloc(&s->dt, n)); HIPCHK(s, dalloc(&s->R, (size_t)4 * n));
     HIPCHK(s, dalloc(&s->tmp, (size_t)4 * n));
@@ -555,11 +714,16 @@ int ql_upload_cloud(ql_solver *s, int64_t n64, const double *x, const double *y,
     HIPCHK(s, dalloc(&s->qmm, (size_t)4 * n));
     HIPCHK(s, dalloc(&s->q32[0], n)); HIPCHK(s, dalloc(&s->q32[1], n));
     HIPCHK(s, dalloc(&s->g32, (size_t)2 * n)); HIPCHK(s, dalloc(&s->qmm32, (size_t)2 * n));
-    HIPCHK(s, dalloc(&s->partial, (size_t)4 * nblk));
     HIPCHK(s, dalloc(&s->fscratch, (size_t)3 * std::max<size_t>(hwall.size(), 1)));
     HIPCHK(s, dalloc(&s->fout, 2)); HIPCHK(s, dalloc(&s->errw, 2));
+    HIPCHK(s, dalloc(&s->case_of, n)); HIPCHK(s, dalloc(&s->uinf, (size_t)4 * ncase));
+    HIPCHK(s, dalloc(&s->case_active, ncase)); HIPCHK(s, dalloc(&s->tile_active, ntile));
+    HIPCHK(s, dalloc(&s->chunk_beg, nchunk + 1)); HIPCHK(s, dalloc(&s->chunk_ptr, ncase + 1));
+    HIPCHK(s, dalloc(&s->part, (size_t)4 * nchunk)); HIPCHK(s, dalloc(&s->inv_nupd, ncase));
+    HIPCHK(s, dalloc(&s->ctr, 1));
 
     hipStream_t st = s->stream;
+    const std::vector<uint8_t> ones_c(ncase, 1), ones_t(ntile, 1);
     HIPCHK(s, hipMemcpyAsync(s->xy, hxy.data(), sizeof(double2) * n, hipMemcpyHostToDevice, st));
     HIPCHK(s, hipMemcpyAsync(s->nrm, hnrm.data(), sizeof(double2) * n, hipMemcpyHostToDevice, st));
     HIPCHK(s, hipMemcpyAsync(s->kind, hkind.data(), n, hipMemcpyHostToDevice, st));
@@ -569,23 +733,31 @@ int ql_upload_cloud(ql_solver *s, int64_t n64, const double *x, const double *y,
     HIPCHK(s, hipMemcpyAsync(s->dperm, perm.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
     if (!hwall.empty())
         HIPCHK(s, hipMemcpyAsync(s->wall, hwall.data(), sizeof(int) * hwall.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(s, hipMemcpyAsync(s->case_of, hcase.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+    HIPCHK(s, hipMemcpyAsync(s->case_active, ones_c.data(), ncase, hipMemcpyHostToDevice, st));
+    HIPCHK(s, hipMemcpyAsync(s->tile_active, ones_t.data(), ntile, hipMemcpyHostToDevice, st));
+    HIPCHK(s, hipMemcpyAsync(s->chunk_beg, cbeg.data(), sizeof(int) * (nchunk + 1), hipMemcpyHostToDevice, st));
+    HIPCHK(s, hipMemcpyAsync(s->chunk_ptr, cptr.data(), sizeof(int) * (ncase + 1), hipMemcpyHostToDevice, st));
+    HIPCHK(s, hipMemcpyAsync(s->inv_nupd, inv_nupd.data(), sizeof(double) * ncase, hipMemcpyHostToDevice, st));
     {
         std::vector<int> thptr, thidx;
         std::vector<uint16_t> tlidx;
-        s->max_slots = build_tiles(n, hptr, hidx, thptr, thidx, tlidx);
-        if (s->max_slots == INT_MAX) {
-            s->max_slots = 1 << 30;  // no tiled kernels for this cloud
-        } else {
-            HIPCHK(s, dalloc(&s->halo_ptr, thptr.size()));
-            HIPCHK(s, dalloc(&s->halo_idx, thidx.size()));
-            HIPCHK(s, dalloc(&s->lidx, tlidx.size()));
-            HIPCHK(s, hipMemcpy(s->halo_ptr, thptr.data(), sizeof(int) * thptr.size(),
+        const int ms = build_tiles(n, kFluxTile, hptr, hidx, thptr, thidx, tlidx);
+        if (ms != INT_MAX) {  // else every flux tile reads from memory
+            s->fmax_slots = ms;
+            s->fslots.resize(thptr.size() - 1);
+            for (size_t t = 0; t + 1 < thptr.size(); ++t)
+                s->fslots[t] = kFluxTile + thptr[t + 1] - thptr[t];
+            HIPCHK(s, dalloc(&s->fhalo_ptr, thptr.size()));
+            HIPCHK(s, dalloc(&s->fhalo_idx, thidx.size()));
+            HIPCHK(s, dalloc(&s->flidx, tlidx.size()));
+            HIPCHK(s, hipMemcpy(s->fhalo_ptr, thptr.data(), sizeof(int) * thptr.size(),
                                 hipMemcpyHostToDevice));
             if (!thidx.empty())
-                HIPCHK(s, hipMemcpy(s->halo_idx, thidx.data(), sizeof(int) * thidx.size(),
+                HIPCHK(s, hipMemcpy(s->fhalo_idx, thidx.data(), sizeof(int) * thidx.size(),
                                     hipMemcpyHostToDevice));
             if (!tlidx.empty())
-                HIPCHK(s, hipMemcpy(s->lidx, tlidx.data(), sizeof(uint16_t) * tlidx.size(),
+                HIPCHK(s, hipMemcpy(s->flidx, tlidx.data(), sizeof(uint16_t) * tlidx.size(),
                                     hipMemcpyHostToDevice));
         }
     }
@@ -596,7 +768,7 @@ int ql_upload_cloud(ql_solver *s, int64_t n64, const double *x, const double *y,
     int rc = reset_err(s);
     if (rc) return rc;
     HIPCHK(s, launch_setup(st, n, s->xy, s->nrm, s->kind, s->ptr, s->idx, s->flag,
-                           nbr_flag ? 0 : 1, s->lsw, s->dmin, s->errw));
+                           nbr_flag ? 0 : 1, s->lsw, s->lsi, s->dmin, s->errw));
     // host buffers above must outlive the asynchronous copies
     rc = sync_and_check(s, "upload");
     if (rc) {
@@ -607,6 +779,24 @@ int ql_upload_cloud(ql_solver *s, int64_t n64, const double *x, const double *y,
     }
     s->has_cloud = true;
     return QL_OK;
+}
+
+int ql_upload_cloud(ql_solver *s, int64_t n64, const double *x, const double *y,
+                    const double *nx, const double *ny, const uint8_t *kind,
+                    const int32_t *nbr_ptr, const int32_t *nbr_idx, const uint8_t *nbr_flag) {
+    const int64_t cp[2] = {0, n64};
+    return upload_impl(s, 1, cp, n64, x, y, nx, ny, kind, nbr_ptr, nbr_idx, nbr_flag, nullptr,
+                       nullptr);
+}
+
+int ql_batch_upload(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int64_t n,
+                    const double *x, const double *y, const double *nx, const double *ny,
+                    const uint8_t *kind, const int32_t *nbr_ptr, const int32_t *nbr_idx,
+                    const double *mach, const double *alpha_deg) {
+    if (!s) return QL_EINVAL;
+    if (!case_ptr || !mach || !alpha_deg) return fail(s, QL_EINVAL, "null case array");
+    return upload_impl(s, ncase, case_ptr, n, x, y, nx, ny, kind, nbr_ptr, nbr_idx, nullptr, mach,
+                       alpha_deg);
 }
 
 int ql_cloud_size(const ql_solver *s, int64_t *n, int64_t *nnz) {
@@ -620,12 +810,23 @@ int ql_init_freestream(ql_solver *s) {
     int st = ensure_ready(s, false);
     if (st) return st;
     (void)hipSetDevice(s->device);
-    const double a = s->prm.alpha_deg * M_PI / 180.0;
-    const double rho = 1.0, u1 = s->prm.mach * std::cos(a), u2 = s->prm.mach * std::sin(a);
-    const double p = 1.0 / s->prm.gamma;
-    const double Uinf[4] = {rho, rho * u1, rho * u2,
-                            p / (s->prm.gamma - 1.0) + 0.5 * rho * (u1 * u1 + u2 * u2)};
-    HIPCHK(s, launch_freestream(s->stream, s->n, s->nrm, s->kind, Uinf, s->U));
+    if (s->ncase == 1) {  // the one-case API follows ql_set_params
+        s->case_mach[0] = s->prm.mach;
+        s->case_alpha[0] = s->prm.alpha_deg;
+    }
+    std::vector<double> uinf((size_t)4 * s->ncase);
+    for (int c = 0; c < s->ncase; ++c) {
+        const double a = s->case_alpha[c] * M_PI / 180.0;
+        const double rho = 1.0, u1 = s->case_mach[c] * std::cos(a), u2 = s->case_mach[c] * std::sin(a);
+        const double p = 1.0 / s->prm.gamma;
+        uinf[4 * c] = rho;
+        uinf[4 * c + 1] = rho * u1;
+        uinf[4 * c + 2] = rho * u2;
+        uinf[4 * c + 3] = p / (s->prm.gamma - 1.0) + 0.5 * rho * (u1 * u1 + u2 * u2);
+    }
+    HIPCHK(s, hipMemcpyAsync(s->uinf, uinf.data(), sizeof(double) * uinf.size(),
+                             hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, launch_freestream(s->stream, s->n, s->nrm, s->kind, s->case_of, s->uinf, s->U));
     st = prep_state(s);
     if (st) return st;
     st = sync_and_check(s, "init_freestream");
@@ -677,40 +878,24 @@ int ql_step(ql_solver *s, int32_t n_iter, double *res_hist) {
     if (n_iter < 0) return fail(s, QL_EINVAL, "n_iter < 0");
     if (n_iter == 0) return QL_OK;
     (void)hipSetDevice(s->device);
-    if (n_iter > s->reshist_cap) {
-        dfree(s->reshist);
-        HIPCHK(s, dalloc(&s->reshist, (size_t)4 * n_iter));
-        s->reshist_cap = n_iter;
-    }
+    if ((st = ensure_history(s, n_iter))) return st;
     const DevCloud c = dev_cloud(s);
     const FlowParams fp = flow_params(s);
-    st = reset_err(s);
-    if (st) return st;
-    const int nblk = num_blocks(s->n);
-    const double inv_nupd = s->n_upd > 0 ? 1.0 / s->n_upd : 0.0;
-    for (int it = 0; it < n_iter; ++it) {
-        for (int rk = 1; rk <= 4; ++rk) {
-            st = run_gradients(s, c, fp.limiter != 0);
-            if (st) return st;
-            Timer t(s, 2);
-            st = launch_stage(s, c, fp, rk, nullptr, rk == 1 ? s->partial : nullptr);
-            if (st) return st;
-            t.done();
-            s->qcur = 1 - s->qcur;
-        }
-        Timer t(s, 3);
-        HIPCHK(s, launch_resnorm(s->stream, nblk, s->partial, inv_nupd, s->reshist + 4 * it));
-        t.done();
-    }
-    std::vector<double> hist((size_t)4 * n_iter);
-    HIPCHK(s, hipMemcpyAsync(hist.data(), s->reshist, sizeof(double) * 4 * n_iter,
-                             hipMemcpyDeviceToHost, s->stream));
+    if ((st = reset_err(s))) return st;
+    if ((st = reset_counter(s))) return st;
+    for (int it = 0; it < n_iter; ++it)
+        if ((st = enqueue_iteration(s, c, fp, s->reshist_cap / s->ncase))) return st;
+    const size_t rows = (size_t)n_iter * s->ncase * 4;
+    std::vector<double> hist(rows);
+    HIPCHK(s, hipMemcpyAsync(hist.data(), s->reshist, sizeof(double) * rows, hipMemcpyDeviceToHost,
+                             s->stream));
     st = sync_and_check(s, "step");
     harvest_timing(s);
     s->has_eval = false;
     if (st) return st;
-    if (res_hist) std::memcpy(res_hist, hist.data(), sizeof(double) * 4 * n_iter);
-    std::memcpy(s->last_res, &hist[(size_t)4 * (n_iter - 1)], sizeof s->last_res);
+    if (res_hist) std::memcpy(res_hist, hist.data(), sizeof(double) * rows);
+    std::memcpy(s->last_res.data(), &hist[rows - (size_t)4 * s->ncase],
+                sizeof(double) * 4 * s->ncase);
     s->has_res = true;
     return QL_OK;
 }
@@ -718,7 +903,7 @@ int ql_step(ql_solver *s, int32_t n_iter, double *res_hist) {
 int ql_residual_norm(const ql_solver *s, double out[4]) {
     if (!s || !out) return QL_EINVAL;
     if (!s->has_res) return QL_ESTATE;
-    std::memcpy(out, s->last_res, sizeof s->last_res);
+    std::memcpy(out, s->last_res.data(), sizeof(double) * 4);
     return QL_OK;
 }
 
@@ -732,12 +917,21 @@ int ql_evaluate(ql_solver *s) {
     if (st) return st;
     st = run_gradients(s, c, true);
     if (st) return st;
-    st = launch_stage(s, c, fp, 0, s->R, nullptr);
+    st = launch_stage(s, c, fp, 0, s->R);
     if (st) return st;
     st = sync_and_check(s, "evaluate");
     harvest_timing(s);
     s->has_eval = (st == QL_OK);
     return st;
+}
+
+int ql_flux_tiles(const ql_solver *s, int32_t *ntile, int32_t *slots) {
+    if (!s || !ntile) return QL_EINVAL;
+    if (!s->has_cloud) return QL_ESTATE;
+    *ntile = (int32_t)s->fslots.size();
+    if (slots)
+        for (size_t t = 0; t < s->fslots.size(); ++t) slots[t] = s->fslots[t];
+    return QL_OK;
 }
 
 int ql_debug_fetch(ql_solver *s, int32_t what, double *out) {
@@ -799,21 +993,131 @@ int ql_debug_flags(ql_solver *s, uint8_t *out) {
     return QL_OK;
 }
 
-int ql_forces(ql_solver *s, double *cl, double *cd) {
-    int st = ensure_ready(s, true);
-    if (st) return st;
-    if (!cl || !cd) return fail(s, QL_EINVAL, "null output");
-    if (s->nw < 3) return fail(s, QL_EINVAL, "fewer than 3 wall points");
-    (void)hipSetDevice(s->device);
-    HIPCHK(s, launch_forces(s->stream, s->nw, s->wall, s->xy, s->nrm, s->U, s->n, s->prm.gamma,
+static int case_forces(ql_solver *s, int c, double *cl, double *cd) {
+    const int w0 = s->wall_lo[c], nw = s->wall_lo[c + 1] - w0;
+    if (nw < 3) return fail(s, QL_EINVAL, "case %d has fewer than 3 wall points", c);
+    HIPCHK(s, launch_forces(s->stream, nw, s->wall + w0, s->xy, s->nrm, s->U, s->n, s->prm.gamma,
                             1.0 / s->prm.gamma, s->fscratch, s->fout));
     double F[2];
     HIPCHK(s, hipMemcpyAsync(F, s->fout, sizeof F, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
-    const double a = s->prm.alpha_deg * M_PI / 180.0;
-    const double qinf = 0.5 * s->prm.mach * s->prm.mach;
+    const double mach = (s->ncase == 1) ? s->prm.mach : s->case_mach[c];
+    const double alpha = (s->ncase == 1) ? s->prm.alpha_deg : s->case_alpha[c];
+    const double a = alpha * M_PI / 180.0;
+    const double qinf = 0.5 * mach * mach;
     *cl = (-F[0] * std::sin(a) + F[1] * std::cos(a)) / qinf;
     *cd = (F[0] * std::cos(a) + F[1] * std::sin(a)) / qinf;
+    return QL_OK;
+}
+
+int ql_forces(ql_solver *s, double *cl, double *cd) {
+    int st = ensure_ready(s, true);
+    if (st) return st;
+    if (!cl || !cd) return fail(s, QL_EINVAL, "null output");
+    (void)hipSetDevice(s->device);
+    return case_forces(s, 0, cl, cd);
+}
+
+int ql_batch_forces(ql_solver *s, double *cl, double *cd) {
+    int st = ensure_ready(s, true);
+    if (st) return st;
+    if (!cl || !cd) return fail(s, QL_EINVAL, "null output");
+    (void)hipSetDevice(s->device);
+    for (int c = 0; c < s->ncase; ++c)
+        if ((st = case_forces(s, c, &cl[c], &cd[c]))) return st;
+    return QL_OK;
+}
+
+int ql_batch_info(const ql_solver *s, int32_t *ncase) {
+    if (!s || !s->has_cloud) return QL_ESTATE;
+    if (ncase) *ncase = s->ncase;
+    return QL_OK;
+}
+
+int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_every, int32_t graph,
+                 int32_t *iters_out, double *res_out) {
+    int st = ensure_ready(s, true);
+    if (st) return st;
+    if (!(drop > 0.0) || max_iter < 0 || check_every < 1)
+        return fail(s, QL_EINVAL, "need drop > 0, max_iter >= 0, check_every >= 1");
+    (void)hipSetDevice(s->device);
+    const int nc = s->ncase, ntile = num_flux_tiles(s->n);
+    const int block = std::min(check_every, std::max(max_iter, 1));
+    if ((st = ensure_history(s, block))) return st;
+    std::vector<uint8_t> active(nc, 1), tile(ntile, 1);
+    std::vector<double> ref(nc, -1.0), last((size_t)4 * nc, 0.0);
+    std::vector<int> iters(nc, 0);
+    HIPCHK(s, hipMemcpyAsync(s->case_active, active.data(), nc, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->tile_active, tile.data(), ntile, hipMemcpyHostToDevice, s->stream));
+    if ((st = reset_err(s))) return st;
+    const DevCloud c = dev_cloud(s);
+    const FlowParams fp = flow_params(s);
+    std::vector<double> hist((size_t)block * nc * 4);
+    int done = 0, nactive = nc;
+    while (done < max_iter && nactive > 0) {
+        const int k = std::min(block, max_iter - done);
+        if ((st = reset_counter(s))) return st;
+        if (graph) {
+            if ((st = capture_iteration(s))) return st;
+            for (int it = 0; it < k; ++it) HIPCHK(s, hipGraphLaunch(s->graph, s->stream));
+        } else {
+            for (int it = 0; it < k; ++it)
+                if ((st = enqueue_iteration(s, c, fp, block))) return st;
+        }
+        HIPCHK(s, hipMemcpyAsync(hist.data(), s->reshist, sizeof(double) * k * nc * 4,
+                                 hipMemcpyDeviceToHost, s->stream));
+        if ((st = sync_and_check(s, "batch_run"))) return st;
+        harvest_timing(s);
+        bool changed = false;
+        for (int cs = 0; cs < nc; ++cs) {
+            if (!active[cs]) continue;
+            for (int r = 0; r < k; ++r) {
+                const double *h = &hist[((size_t)r * nc + cs) * 4];
+                iters[cs] += 1;
+                std::memcpy(&last[4 * cs], h, sizeof(double) * 4);
+                if (ref[cs] < 0.0) ref[cs] = h[0];
+                if (h[0] <= drop * ref[cs]) {
+                    active[cs] = 0;
+                    --nactive;
+                    changed = true;
+                    break;
+                }
+            }
+        }
+        done += k;
+        if (changed && nactive > 0) {
+            // freeze retired cases; skip tiles that hold only retired points
+            for (int t = 0; t < ntile; ++t) {
+                const int b = t * kFluxTile, e = std::min(s->n, b + kFluxTile) - 1;
+                int c0 = 0;
+                while (s->case_lo[c0 + 1] <= b) ++c0;
+                int c1 = c0;
+                while (s->case_lo[c1 + 1] <= e) ++c1;
+                uint8_t any = 0;
+                for (int cs = c0; cs <= c1; ++cs) any |= active[cs];
+                tile[t] = any;
+            }
+            HIPCHK(s, hipMemcpyAsync(s->case_active, active.data(), nc, hipMemcpyHostToDevice,
+                                     s->stream));
+            HIPCHK(s, hipMemcpyAsync(s->tile_active, tile.data(), ntile, hipMemcpyHostToDevice,
+                                     s->stream));
+            HIPCHK(s, hipStreamSynchronize(s->stream));
+        }
+    }
+    // leave every case active for later calls, and rebuild the start-of-
+    // iteration data (q, time step, Un) from U: skipped tiles did not keep
+    // the q buffers of retired cases current
+    std::fill(active.begin(), active.end(), 1);
+    std::fill(tile.begin(), tile.end(), 1);
+    HIPCHK(s, hipMemcpyAsync(s->case_active, active.data(), nc, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->tile_active, tile.data(), ntile, hipMemcpyHostToDevice, s->stream));
+    if ((st = prep_state(s))) return st;
+    if ((st = sync_and_check(s, "batch_run"))) return st;
+    s->has_eval = false;
+    s->last_res = last;
+    s->has_res = done > 0;
+    if (iters_out) std::copy(iters.begin(), iters.end(), iters_out);
+    if (res_out) std::copy(last.begin(), last.end(), res_out);
     return QL_OK;
 }
 

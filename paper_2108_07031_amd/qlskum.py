@@ -28,13 +28,16 @@ QL_SPLIT_S_PLUS, QL_SPLIT_S_MINUS, QL_SPLIT_N_PLUS, QL_SPLIT_N_MINUS = 1, 2, 4, 
 EXPORTS = ("ql_default_params", "ql_create", "ql_destroy", "ql_upload_cloud", "ql_set_params",
            "ql_init_freestream", "ql_set_state", "ql_step", "ql_residual_norm",
            "ql_fetch_state", "ql_forces", "ql_last_error", "ql_evaluate", "ql_debug_fetch",
-           "ql_debug_flags", "ql_cloud_size", "ql_set_timing", "ql_kernel_time")
+           "ql_debug_flags", "ql_cloud_size", "ql_set_timing", "ql_kernel_time",
+           "ql_batch_upload", "ql_batch_info", "ql_batch_run", "ql_batch_forces",
+           "ql_flux_tiles")
 
 
 class ql_params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("mach", C.c_double), ("alpha_deg", C.c_double),
                 ("cfl", C.c_double), ("n_inner", C.c_int32), ("limiter", C.c_int32),
-                ("venkat_k", C.c_double), ("precision", C.c_int32), ("reorder", C.c_int32)]
+                ("venkat_k", C.c_double), ("precision", C.c_int32), ("reorder", C.c_int32),
+                ("flux_lds", C.c_int32)]
 
 
 class QLError(RuntimeError):
@@ -69,6 +72,11 @@ def _load():
     lib.ql_cloud_size.argtypes = [vp, P(i64), P(i64)]
     lib.ql_set_timing.argtypes = [vp, i32]
     lib.ql_kernel_time.argtypes = [vp, i32, P(d), P(i64)]
+    lib.ql_batch_upload.argtypes = [vp, i32, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.ql_batch_info.argtypes = [vp, P(i32)]
+    lib.ql_batch_run.argtypes = [vp, d, i32, i32, i32, vp, vp]
+    lib.ql_batch_forces.argtypes = [vp, vp, vp]
+    lib.ql_flux_tiles.argtypes = [vp, P(i32), vp]
     for name in EXPORTS:
         if name not in ("ql_default_params", "ql_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -151,11 +159,50 @@ def ql_set_state(s, U, project_wall=False):
     return _check(s, lib.ql_set_state(s, _dev_ptr(U), 1, int(bool(project_wall))))
 
 
+def ql_batch_info(s):
+    nc = C.c_int32()
+    _check(s, lib.ql_batch_info(s, C.byref(nc)))
+    return nc.value
+
+
 def ql_step(s, n_iter, want_history=True):
-    """Returns the (n_iter, 4) residual history (or None)."""
-    hist = np.zeros((max(n_iter, 1), 4)) if want_history else None
+    """Returns the residual history, (n_iter, 4) for one case or
+    (n_iter, ncase, 4) for a batched cloud (or None)."""
+    nc = ql_batch_info(s)
+    hist = np.zeros((max(n_iter, 1), nc, 4)) if want_history else None
     _check(s, lib.ql_step(s, int(n_iter), hist.ctypes.data if want_history else None))
-    return hist[:n_iter] if want_history else None
+    if not want_history:
+        return None
+    return hist[:n_iter, 0] if nc == 1 else hist[:n_iter]
+
+
+def ql_batch_upload(s, case_ptr, x, y, nx, ny, kind, nbr_ptr, nbr_idx, mach, alpha_deg):
+    cp = np.ascontiguousarray(case_ptr, dtype=np.int64)
+    keep = [_host(x, np.float64), _host(y, np.float64), _host(nx, np.float64),
+            _host(ny, np.float64), _host(kind, np.uint8), _host(nbr_ptr, np.int32),
+            _host(nbr_idx, np.int32)]
+    m = np.ascontiguousarray(mach, dtype=np.float64)
+    a = np.ascontiguousarray(alpha_deg, dtype=np.float64)
+    n = keep[0][0].shape[0]
+    return _check(s, lib.ql_batch_upload(s, cp.shape[0] - 1, cp.ctypes.data, n,
+                                         *(k[1] for k in keep), m.ctypes.data, a.ctypes.data))
+
+
+def ql_batch_run(s, drop, max_iter, check_every=100, graph=True):
+    """Returns (iterations per case, last residual norms (ncase, 4))."""
+    nc = ql_batch_info(s)
+    iters = np.zeros(nc, np.int32)
+    res = np.zeros((nc, 4))
+    _check(s, lib.ql_batch_run(s, float(drop), int(max_iter), int(check_every), int(bool(graph)),
+                               iters.ctypes.data, res.ctypes.data))
+    return iters, res
+
+
+def ql_batch_forces(s):
+    nc = ql_batch_info(s)
+    cl, cd = np.zeros(nc), np.zeros(nc)
+    _check(s, lib.ql_batch_forces(s, cl.ctypes.data, cd.ctypes.data))
+    return cl, cd
 
 
 def ql_residual_norm(s):
@@ -209,6 +256,15 @@ def ql_debug_fetch(s, what):
     return out
 
 
+def ql_flux_tiles(s):
+    """Records in each flux tile's LDS image, int32[ntile]."""
+    nt = C.c_int32()
+    _check(s, lib.ql_flux_tiles(s, C.byref(nt), None))
+    out = np.empty(nt.value, np.int32)
+    _check(s, lib.ql_flux_tiles(s, C.byref(nt), out.ctypes.data))
+    return out
+
+
 def ql_debug_flags(s):
     _, nnz = ql_cloud_size(s)
     out = np.empty(nnz, np.uint8)
@@ -246,6 +302,24 @@ class Solver:
         if cloud is not None:
             self.upload(cloud)
 
+    def upload_batch(self, clouds, mach, alpha_deg):
+        """Concatenate independent clouds into one batched upload."""
+        offs = np.cumsum([0] + [c.n for c in clouds])
+        eoffs = np.cumsum([0] + [c.nnz for c in clouds])
+        cat = lambda f: np.concatenate([getattr(c, f) for c in clouds])
+        ptr = np.concatenate([c.nbr_ptr[:-1].astype(np.int64) + e for c, e in zip(clouds, eoffs)]
+                             + [np.array([eoffs[-1]])])
+        idx = np.concatenate([c.nbr_idx.astype(np.int64) + o for c, o in zip(clouds, offs)])
+        ql_batch_upload(self.h, offs, cat("x"), cat("y"), cat("nx"), cat("ny"), cat("kind"),
+                        ptr, idx, mach, alpha_deg)
+        return offs
+
+    def batch_run(self, drop, max_iter, check_every=100, graph=True):
+        return ql_batch_run(self.h, drop, max_iter, check_every, graph)
+
+    def batch_forces(self):
+        return ql_batch_forces(self.h)
+
     def upload(self, cloud, nbr_flag=None):
         ql_upload_cloud(self.h, cloud.x, cloud.y, cloud.nx, cloud.ny, cloud.kind,
                         cloud.nbr_ptr, cloud.nbr_idx, nbr_flag)
@@ -275,6 +349,9 @@ class Solver:
 
     def flags(self):
         return ql_debug_flags(self.h)
+
+    def flux_tiles(self):
+        return ql_flux_tiles(self.h)
 
     def close(self):
         if self.h:

@@ -1,0 +1,17 @@
+// Host-side evaluation of the solver's erfc approximation on arguments read
+// from stdin (one per line); prints erfc in FP64 and FP32 paths.
+#include <cmath>
+#include <cstdio>
+
+#include "../paper_2108_07031_amd/csrc/qlskum_erfc.h"
+
+int main() {
+    double y;
+    while (std::scanf("%lf", &y) == 1) {
+        const double e64 = 2.0 * ql::half_erfc(y, ql::gauss(y));
+        const float yf = (float)y;
+        const float e32 = 2.0f * ql::half_erfc_f(yf, std::exp(-yf * yf));
+        std::printf("%.17e %.9e\n", e64, (double)e32);
+    }
+    return 0;
+}

@@ -1,0 +1,72 @@
+"""The flux sweep's LDS staging changes where records are read from, never
+the arithmetic: every point's residual is summed over its entries in one
+fixed order whether its tile's image sits in LDS or is read from memory, so
+results are bitwise identical across LDS budgets (all tiles staged, none
+staged, and budgets in between where tiles of both kinds share a launch).
+"""
+import numpy as np
+import pytest
+
+from tests._common import cloud, smooth_state
+
+pytestmark = pytest.mark.gpu
+
+# record bytes of the flux tile image: (precision, limiter) -> bytes
+REC = {(0, 1): 176, (0, 0): 112, (1, 1): 96, (1, 0): 64}
+
+
+@pytest.fixture(scope="module")
+def ql():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2108_07031_amd import qlskum
+    return qlskum
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("limiter", [0, 1])
+def test_flux_lds_budget_invariance(ql, precision, limiter):
+    _say(f"lds budgets precision={precision} limiter={limiter}")
+    c = cloud("jitter")
+    # the unlimited scheme is run subsonic (at M 0.85 it forms shocks)
+    flow = dict(mach=0.85, alpha_deg=1.0) if limiter else dict(mach=0.63, alpha_deg=2.0)
+    U0 = smooth_state(c, **flow)
+    s = ql.Solver(c)
+    slots = s.flux_tiles()
+    s.close()
+    rec = REC[(precision, limiter)]
+    # 0: library default; 16: no tile staged; the quartiles of the image
+    # sizes: staged and unstaged tiles in the same launch
+    q1, q3 = np.percentile(slots, [25, 75]).astype(int)
+    budgets = [0, 16, int(q1) * rec, int(q3) * rec]
+    staged = [(slots * rec <= b).mean() for b in budgets[2:]]
+    _say(f"  tiles {slots.size}, slots {slots.min()}..{slots.max()}, staged {staged}")
+    assert all(0.0 < f < 1.0 for f in staged)
+    out = []
+    for b in budgets:
+        s = ql.Solver(c, precision=precision, limiter=limiter, flux_lds=b, **flow)
+        s.set_state(U0)
+        R = s.evaluate()["R"]
+        s.set_state(U0)
+        h = s.step(15)
+        out.append((R, h, s.fetch_state()))
+        s.close()
+    for b, (R, h, U) in zip(budgets[1:], out[1:]):
+        np.testing.assert_array_equal(R, out[0][0], err_msg=f"budget {b}")
+        np.testing.assert_array_equal(h, out[0][1], err_msg=f"budget {b}")
+        np.testing.assert_array_equal(U, out[0][2], err_msg=f"budget {b}")
+
+
+def test_flux_lds_budget_rejected(ql):
+    _say("lds budget out of range")
+    s = ql.Solver()
+    with pytest.raises(ql.QLError):
+        s.set_params(flux_lds=-1)
+    with pytest.raises(ql.QLError):
+        s.set_params(flux_lds=200 * 1024)
+    s.close()
