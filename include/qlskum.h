@@ -183,7 +183,10 @@ int ql_batch_upload(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int64_
 int ql_batch_info(const ql_solver *s, int32_t *ncase);
 
 /* Iterate all cases until each one's density residual norm falls to
- * drop x its first iteration's norm, or max_iter iterations.  Every
+ * drop x its reference norm, or max_iter iterations.  The reference of case
+ * c is ref_res[c] when ref_res is not NULL (e.g. the freestream residual
+ * that ql_warm_start reports), else the norm of the first iteration of this
+ * call.  Every
  * check_every iterations the norms are read back; converged cases retire:
  * their points stop updating and workgroups holding only retired points
  * skip every sweep, while the other cases go on.  graph != 0 captures one
@@ -191,12 +194,79 @@ int ql_batch_info(const ql_solver *s, int32_t *ncase);
  * parameter or buffer changes) and replays it.  iters_out[c] (nullable)
  * receives the iteration at which case c reached the drop (or the
  * iterations run), res_out[c][4] (nullable) its last norms.
- * Errors: as ql_step; QL_EINVAL (drop <= 0, max_iter < 0, check_every < 1). */
+ * Errors: as ql_step; QL_EINVAL (drop <= 0, max_iter < 0, check_every < 1,
+ * a reference <= 0 or not finite). */
 int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_every, int32_t graph,
-                 int32_t *iters_out, double *res_out);
+                 const double *ref_res, int32_t *iters_out, double *res_out);
 
 /* Lift and drag of every case (as ql_forces), cl[ncase], cd[ncase]. */
 int ql_batch_forces(ql_solver *s, double *cl, double *cd);
+
+/* --- warm start: a learned initial state ------------------------------- */
+
+/* A multilayer perceptron on the device, widths[0] inputs -> hidden layers
+ * of widths[1 .. nwidth-2] with tanh -> widths[nwidth-1] linear outputs,
+ * evaluated and trained with bfloat16 operands on the matrix cores (FP32
+ * accumulation; bias, tanh, loss and Adam in FP32).  The initial state of
+ * an explicit solve is arbitrary; a network that maps point features
+ * (position, wall distance, flow condition) to the converged primitive
+ * fields gives a start closer to the solution (spec item: learned
+ * warm start).  The network object is separate from the solver; max_batch
+ * bounds the rows of one training step (inference is chunked).  The
+ * library owns all device buffers; hip_stream as in ql_create.
+ * Weights are one FP32 vector: for each layer l, W_l row-major
+ * (widths[l] x widths[l+1]) then b_l (widths[l+1]).
+ * Errors: QL_EINVAL (widths outside 1..4096, fewer than 2, max_batch
+ * outside 1..2^26), QL_EDEVICE, QL_ENOMEM. */
+typedef struct ql_mlp ql_mlp;
+int ql_mlp_create(ql_mlp **out, int32_t device, void *hip_stream, const int32_t *widths,
+                  int32_t nwidth, int64_t max_batch);
+int ql_mlp_destroy(ql_mlp *m);
+const char *ql_mlp_last_error(const ql_mlp *m);
+int ql_mlp_num_params(const ql_mlp *m, int64_t *np);
+
+/* Host FP32 weights in / out.  Setting them restarts Adam (moments 0).
+ * Errors: QL_EINVAL, QL_ENONFINITE (a weight is not finite), QL_ESTATE
+ * (get before any set). */
+int ql_mlp_set_weights(ql_mlp *m, const float *w);
+int ql_mlp_get_weights(ql_mlp *m, float *w);
+
+/* Y[n][w_out] = network(X[n][w_in]); X, Y device FP32, row-major, enqueued
+ * on the network's stream.  Errors: QL_EINVAL, QL_ESTATE (no weights). */
+int ql_mlp_forward(ql_mlp *m, const float *X, float *Y, int64_t n);
+
+/* Mean squared error over the n x w_out outputs of one batch (device X, T;
+ * 1 <= n <= max_batch) and its gradient: *loss (nullable), grad[np] (host,
+ * nullable; the weight layout).  ql_mlp_train_step also applies one Adam
+ * step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) to the FP32
+ * master weights.  Both synchronise when they return values. */
+int ql_mlp_gradient(ql_mlp *m, const float *X, const float *T, int64_t n, float *grad,
+                    double *loss);
+int ql_mlp_train_step(ql_mlp *m, const float *X, const float *T, int64_t n, float lr,
+                      double *loss);
+int ql_mlp_sync(ql_mlp *m);
+
+/* Distance of every point to the nearest wall point of its case, host
+ * d[n] in caller order (+inf for a case without wall points).
+ * Errors: QL_ESTATE (no cloud), QL_EINVAL. */
+int ql_wall_distance(ql_solver *s, double *d);
+
+/* Warm start of every case of the uploaded cloud.  X (device FP32
+ * [n][w_in], caller order) are the network's inputs; its outputs are the
+ * standardised (rho, u1, u2, p): prim = out_scale[k] + out_scale[4+k] * y_k.
+ * Density and pressure are held at or above rel_floor times their
+ * freestream values, wall points get the wall projection, outer points keep
+ * the freestream.  Then, per case, the stage-1 residual norms of this warm
+ * state and of the freestream are compared; a case starts warm only if its
+ * warm density-residual norm is finite and not larger than the cold one
+ * (and no point of it failed), else from the freestream.  res_cold and
+ * res_warm ([ncase][4], nullable) receive both norms, used[ncase]
+ * (nullable) the choice.  The state is then set as by ql_set_state.
+ * Errors: QL_EINVAL (network without weights or not 4 outputs, NULL
+ * arrays, rel_floor outside (0, 1)), QL_ESTATE, device errors; a failure
+ * of the freestream evaluation is reported as by ql_step. */
+int ql_warm_start(ql_solver *s, ql_mlp *m, const float *X, const float *out_scale,
+                  double rel_floor, double *res_cold, double *res_warm, int32_t *used);
 
 /* --- inspection and timing (tests, benchmarks) ------------------------- */
 

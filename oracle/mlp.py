@@ -116,3 +116,37 @@ def forward_bf16(w, widths, X):
         else:
             return z
     raise AssertionError("network without layers")
+
+
+def loss_grad_bf16(w, widths, X, T):
+    """The device's training arithmetic: the forward pass of forward_bf16
+    (hidden activations kept in bfloat16), output error
+    d_L = bf16(2 (y - t) / (B w_L)), and for each layer
+        dW_l = a_{l-1}^T d_l,   db_l = sum_rows d_l         (FP32 results)
+        d_{l-1} = bf16((d_l bf16(W_l)^T) * (1 - a_{l-1}^2))
+    with bfloat16 operands of every product.  Returns (loss, flat FP32
+    gradient); products are formed in FP64 and rounded once to FP32."""
+    layers = unflatten(np.asarray(w, np.float32), widths)
+    acts = [bf16(X)]
+    for l, (W, b) in enumerate(layers):
+        z = (acts[-1].astype(np.float64) @ bf16(W).astype(np.float64)).astype(np.float32) + b
+        if l < len(layers) - 1:
+            acts.append(bf16(np.tanh(z)))
+        else:
+            y = z
+    T = np.asarray(T, np.float32)
+    cnt = y.size
+    diff = (y - T).astype(np.float32)
+    loss = float(np.sum(diff.astype(np.float64) ** 2) / cnt)
+    d = bf16(np.float32(2.0 / cnt) * diff)
+    grads = [None] * len(layers)
+    for l in range(len(layers) - 1, -1, -1):
+        W, _ = layers[l]
+        a_prev = acts[l]
+        gW = (a_prev.T.astype(np.float64) @ d.astype(np.float64)).astype(np.float32)
+        gb = d.astype(np.float64).sum(axis=0).astype(np.float32)
+        grads[l] = (gW, gb)
+        if l > 0:
+            v = (d.astype(np.float64) @ bf16(W).T.astype(np.float64)).astype(np.float32)
+            d = bf16(v * (np.float32(1.0) - a_prev * a_prev))
+    return loss, flatten(grads)

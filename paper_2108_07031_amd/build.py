@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqlskum.so")
-SOURCES = ["qlskum_kernels.hip", "qlskum_runtime.cpp"]
+SOURCES = ["qlskum_kernels.hip", "qlskum_runtime.cpp", "qlskum_mlp.hip",
+           "qlskum_mlp_runtime.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed FP32 instructions are kept out of every code object

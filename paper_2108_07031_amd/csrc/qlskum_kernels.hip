@@ -403,6 +403,10 @@ hipError_t launch_prep(hipStream_t st, const DevCloud &c, const FlowParams &fp, 
 // ---------------------------------------------------------------------------
 namespace {
 
+// entries per lane whose indices a gradient sweep loads before using them
+// (interior points have 24 neighbours: two chunks of 3 per lane)
+constexpr int kChunk = 3;
+
 __device__ __forceinline__ double lane_group_max(double v) {
     v = fmax(v, __shfl_xor(v, 1, 64));
     return fmax(v, __shfl_xor(v, 2, 64));
@@ -456,13 +460,25 @@ __global__ void __launch_bounds__(kBlock) k_grad0(DevCloud cl, int cap,
     if (cl.tile_active && !cl.tile_active[t]) return;
     const TileInfo ti = tile_info(cl, t, cap);
     if (ti.in_lds) {
-        for (int e = threadIdx.x; e < 2 * ti.ns; e += kBlock) {
-            const int pt = slot_point(cl, ti, e >> 1);
-            if (pt >= 0) lds[kRec * (e >> 1) + (e & 1)] = q[2 * pt + (e & 1)];
-        }
-        for (int s = threadIdx.x; s < ti.ns; s += kBlock) {
-            const int pt = slot_point(cl, ti, s);
-            if (pt >= 0) lds[kRec * s + 2] = cl.xy[pt];
+        // one whole record per slot and lane, two slots per pass: all loads
+        // of a pass are independent
+        for (int s0 = threadIdx.x; s0 < ti.ns; s0 += 2 * kBlock) {
+            const int s1 = s0 + kBlock;
+            const int p0 = slot_point(cl, ti, s0);
+            const int p1 = (s1 < ti.ns) ? slot_point(cl, ti, s1) : -1;
+            const int c0 = p0 >= 0 ? p0 : 0, c1 = p1 >= 0 ? p1 : 0;  // in-range reads
+            const double2 a0 = q[2 * c0], a1 = q[2 * c0 + 1], a2 = cl.xy[c0];
+            const double2 b0 = q[2 * c1], b1 = q[2 * c1 + 1], b2 = cl.xy[c1];
+            if (p0 >= 0) {
+                lds[kRec * s0] = a0;
+                lds[kRec * s0 + 1] = a1;
+                lds[kRec * s0 + 2] = a2;
+            }
+            if (p1 >= 0) {
+                lds[kRec * s1] = b0;
+                lds[kRec * s1 + 1] = b1;
+                lds[kRec * s1 + 2] = b2;
+            }
         }
     }
     __syncthreads();
@@ -483,27 +499,39 @@ __global__ void __launch_bounds__(kBlock) k_grad0(DevCloud cl, int cap,
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) mx[r] = mn[r] = qp[r];
+        // entries in chunks of kChunk per lane, their indices loaded first.
+        // Past the list's end an entry refers to p itself: dx = dy = dq = 0
+        // add exactly +0 to the sums and leave the bounds unchanged.
         const int k1 = cl.ptr[p + 1];
-        for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
-            double qi[4];
-            double2 Q;
-            if (ti.in_lds) {
-                const double2 *r = lds + kRec * (int)cl.flidx[k];
-                qi[0] = r[0].x; qi[1] = r[0].y; qi[2] = r[1].x; qi[3] = r[1].y;
-                Q = r[2];
-            } else {
-                const int i = cl.idx[k];
-                load4(q, i, qi);
-                Q = cl.xy[i];
-            }
-            const double dx = Q.x - P.x, dy = Q.y - P.y;
+        const int self = ti.in_lds ? j : p;
+        for (int k0 = cl.ptr[p] + sub; k0 < k1; k0 += kChunk * kFluxLanes) {
+            int li[kChunk];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const double dq = qi[r] - qp[r];
-                sx[r] = fma(dx, dq, sx[r]);
-                sy[r] = fma(dy, dq, sy[r]);
-                mx[r] = fmax(mx[r], qi[r]);
-                mn[r] = fmin(mn[r], qi[r]);
+            for (int u = 0; u < kChunk; ++u) {
+                const int k = k0 + u * kFluxLanes;
+                li[u] = (k < k1) ? (ti.in_lds ? (int)cl.flidx[k] : cl.idx[k]) : self;
+            }
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                double qi[4];
+                double2 Q;
+                if (ti.in_lds) {
+                    const double2 *r = lds + kRec * li[u];
+                    qi[0] = r[0].x; qi[1] = r[0].y; qi[2] = r[1].x; qi[3] = r[1].y;
+                    Q = r[2];
+                } else {
+                    load4(q, li[u], qi);
+                    Q = cl.xy[li[u]];
+                }
+                const double dx = Q.x - P.x, dy = Q.y - P.y;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double dq = qi[r] - qp[r];
+                    sx[r] = fma(dx, dq, sx[r]);
+                    sy[r] = fma(dy, dq, sy[r]);
+                    mx[r] = fmax(mx[r], qi[r]);
+                    mn[r] = fmin(mn[r], qi[r]);
+                }
             }
         }
     }
@@ -547,13 +575,23 @@ __global__ void __launch_bounds__(kBlock) k_gradk(DevCloud cl, int cap,
     if (cl.tile_active && !cl.tile_active[t]) return;
     const TileInfo ti = tile_info(cl, t, cap);
     if (ti.in_lds) {
-        for (int e = threadIdx.x; e < 4 * ti.ns; e += kBlock) {
-            const int pt = slot_point(cl, ti, e >> 2);
-            if (pt >= 0) lds[kRec * (e >> 2) + (e & 3)] = gprev[4 * pt + (e & 3)];
-        }
-        for (int s = threadIdx.x; s < ti.ns; s += kBlock) {
-            const int pt = slot_point(cl, ti, s);
-            if (pt >= 0) lds[kRec * s + 4] = cl.xy[pt];
+        for (int s0 = threadIdx.x; s0 < ti.ns; s0 += 2 * kBlock) {
+            const int s1 = s0 + kBlock;
+            const int p0 = slot_point(cl, ti, s0);
+            const int p1 = (s1 < ti.ns) ? slot_point(cl, ti, s1) : -1;
+            const int c0 = p0 >= 0 ? p0 : 0, c1 = p1 >= 0 ? p1 : 0;  // in-range reads
+            const double2 a0 = gprev[4 * c0], a1 = gprev[4 * c0 + 1], a2 = gprev[4 * c0 + 2],
+                          a3 = gprev[4 * c0 + 3], a4 = cl.xy[c0];
+            const double2 b0 = gprev[4 * c1], b1 = gprev[4 * c1 + 1], b2 = gprev[4 * c1 + 2],
+                          b3 = gprev[4 * c1 + 3], b4 = cl.xy[c1];
+            if (p0 >= 0) {
+                double2 *d = lds + kRec * s0;
+                d[0] = a0; d[1] = a1; d[2] = a2; d[3] = a3; d[4] = a4;
+            }
+            if (p1 >= 0) {
+                double2 *d = lds + kRec * s1;
+                d[0] = b0; d[1] = b1; d[2] = b2; d[3] = b3; d[4] = b4;
+            }
         }
     }
     __syncthreads();
@@ -575,29 +613,39 @@ __global__ void __launch_bounds__(kBlock) k_gradk(DevCloud cl, int cap,
             load8(gprev, p, gp);
             P = cl.xy[p];
         }
+        // chunks as in k_grad0 (an entry past the end refers to p: +0)
         const int k1 = cl.ptr[p + 1];
-        for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
-            double gi[8];
-            double2 Q;
-            if (ti.in_lds) {
-                const double2 *r = lds + kRec * (int)cl.flidx[k];
+        const int self = ti.in_lds ? j : p;
+        for (int k0 = cl.ptr[p] + sub; k0 < k1; k0 += kChunk * kFluxLanes) {
+            int li[kChunk];
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    gi[2 * m] = r[m].x;
-                    gi[2 * m + 1] = r[m].y;
-                }
-                Q = r[4];
-            } else {
-                const int i = cl.idx[k];
-                load8(gprev, i, gi);
-                Q = cl.xy[i];
+            for (int u = 0; u < kChunk; ++u) {
+                const int k = k0 + u * kFluxLanes;
+                li[u] = (k < k1) ? (ti.in_lds ? (int)cl.flidx[k] : cl.idx[k]) : self;
             }
-            const double dx = Q.x - P.x, dy = Q.y - P.y;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const double f = fma(dx, gi[r] - gp[r], dy * (gi[4 + r] - gp[4 + r]));
-                sx[r] = fma(dx, f, sx[r]);
-                sy[r] = fma(dy, f, sy[r]);
+            for (int u = 0; u < kChunk; ++u) {
+                double gi[8];
+                double2 Q;
+                if (ti.in_lds) {
+                    const double2 *r = lds + kRec * li[u];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        gi[2 * m] = r[m].x;
+                        gi[2 * m + 1] = r[m].y;
+                    }
+                    Q = r[4];
+                } else {
+                    load8(gprev, li[u], gi);
+                    Q = cl.xy[li[u]];
+                }
+                const double dx = Q.x - P.x, dy = Q.y - P.y;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double f = fma(dx, gi[r] - gp[r], dy * (gi[4 + r] - gp[4 + r]));
+                    sx[r] = fma(dx, f, sx[r]);
+                    sy[r] = fma(dy, f, sy[r]);
+                }
             }
         }
     }

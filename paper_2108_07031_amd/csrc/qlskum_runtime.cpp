@@ -23,6 +23,12 @@
 #include "../../include/qlskum.h"
 #include "qlskum_internal.h"
 
+namespace ql {  // the warm-start network's runtime (qlskum_mlp_runtime.cpp)
+hipStream_t mlp_stream(const ql_mlp *m);
+int mlp_width(const ql_mlp *m, int end);
+bool mlp_ready(const ql_mlp *m);
+}  // namespace ql
+
 using namespace ql;
 
 namespace {
@@ -77,6 +83,9 @@ struct ql_solver {
     std::vector<int> fslots;  // image size (records) of every flux tile
     double *reshist = nullptr, *fscratch = nullptr, *fout = nullptr;
     int *case_of = nullptr, *chunk_beg = nullptr, *chunk_ptr = nullptr, *ctr = nullptr;
+    int *dwall_lo = nullptr, *wctr = nullptr;  // warm start: wall ranges, residual row counter
+    uint8_t *wsel = nullptr;                    // warm start: per-case choice
+    double *wres = nullptr;                     // warm start: [2][ncase][4] residual norms
     uint8_t *case_active = nullptr, *tile_active = nullptr;
     double *uinf = nullptr, *part = nullptr, *inv_nupd = nullptr;
     int nchunk = 0;
@@ -86,6 +95,7 @@ struct ql_solver {
     int err_init[2] = {INT_MAX, 0};  // source of the error-word reset copies
     int qcur = 0, gfin = 0;
     std::vector<double> last_res;  // [ncase][4]
+    std::vector<double> uinf_host;  // [ncase][4], source of the s->uinf copy
 
     // one pseudo-time iteration captured as a graph (batched runs)
     hipGraphExec_t graph = nullptr;
@@ -142,6 +152,7 @@ void free_cloud(ql_solver *s) {
     dfree(s->fhalo_ptr); dfree(s->fhalo_idx); dfree(s->flidx);
     dfree(s->q32[0]); dfree(s->q32[1]); dfree(s->g32); dfree(s->qmm32);
     dfree(s->case_of); dfree(s->chunk_beg); dfree(s->chunk_ptr); dfree(s->ctr);
+    dfree(s->dwall_lo); dfree(s->wctr); dfree(s->wsel); dfree(s->wres);
     dfree(s->case_active); dfree(s->tile_active); dfree(s->uinf); dfree(s->part);
     dfree(s->inv_nupd);
     if (s->graph) (void)hipGraphExecDestroy(s->graph);
@@ -362,10 +373,10 @@ struct Timer {
 
 // LDS bytes a q-derivative workgroup stages its tile image in (records of
 // 48 and 80 bytes).  Sized so that the workgroups the kernels' register use
-// allows per CU (6 and 7 of 256 lanes) stay resident in 160 KB of LDS; the
-// rare tiles with larger images read from memory.
-constexpr int kGrad0Lds = 24 * 1024;
-constexpr int kGradkLds = 22 * 1024;
+// allows per CU (4 of 256 lanes) stay resident in 160 KB of LDS; the rare
+// tiles with larger images read from memory.
+constexpr int kGrad0Lds = 32 * 1024;
+constexpr int kGradkLds = 36 * 1024;
 
 // One stage's q-derivatives: first pass + n_inner Jacobi iterations; leaves
 // the final iterate in g[gfin].
@@ -721,6 +732,8 @@ static int upload_impl(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int
     HIPCHK(s, dalloc(&s->chunk_beg, nchunk + 1)); HIPCHK(s, dalloc(&s->chunk_ptr, ncase + 1));
     HIPCHK(s, dalloc(&s->part, (size_t)4 * nchunk)); HIPCHK(s, dalloc(&s->inv_nupd, ncase));
     HIPCHK(s, dalloc(&s->ctr, 1));
+    HIPCHK(s, dalloc(&s->dwall_lo, ncase + 1)); HIPCHK(s, dalloc(&s->wctr, 1));
+    HIPCHK(s, dalloc(&s->wsel, ncase)); HIPCHK(s, dalloc(&s->wres, (size_t)8 * ncase));
 
     hipStream_t st = s->stream;
     const std::vector<uint8_t> ones_c(ncase, 1), ones_t(ntile, 1);
@@ -734,6 +747,8 @@ static int upload_impl(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int
     if (!hwall.empty())
         HIPCHK(s, hipMemcpyAsync(s->wall, hwall.data(), sizeof(int) * hwall.size(), hipMemcpyHostToDevice, st));
     HIPCHK(s, hipMemcpyAsync(s->case_of, hcase.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+    HIPCHK(s, hipMemcpyAsync(s->dwall_lo, wall_lo.data(), sizeof(int) * (ncase + 1),
+                             hipMemcpyHostToDevice, st));
     HIPCHK(s, hipMemcpyAsync(s->case_active, ones_c.data(), ncase, hipMemcpyHostToDevice, st));
     HIPCHK(s, hipMemcpyAsync(s->tile_active, ones_t.data(), ntile, hipMemcpyHostToDevice, st));
     HIPCHK(s, hipMemcpyAsync(s->chunk_beg, cbeg.data(), sizeof(int) * (nchunk + 1), hipMemcpyHostToDevice, st));
@@ -806,6 +821,24 @@ int ql_cloud_size(const ql_solver *s, int64_t *n, int64_t *nnz) {
     return QL_OK;
 }
 
+// Conserved freestream of every case into s->uinf (rho = 1, p = 1/gamma).
+static int upload_freestream(ql_solver *s) {
+    s->uinf_host.assign((size_t)4 * s->ncase, 0.0);
+    for (int c = 0; c < s->ncase; ++c) {
+        const double a = s->case_alpha[c] * M_PI / 180.0;
+        const double rho = 1.0, u1 = s->case_mach[c] * std::cos(a), u2 = s->case_mach[c] * std::sin(a);
+        const double p = 1.0 / s->prm.gamma;
+        double *u = &s->uinf_host[4 * c];
+        u[0] = rho;
+        u[1] = rho * u1;
+        u[2] = rho * u2;
+        u[3] = p / (s->prm.gamma - 1.0) + 0.5 * rho * (u1 * u1 + u2 * u2);
+    }
+    HIPCHK(s, hipMemcpyAsync(s->uinf, s->uinf_host.data(), sizeof(double) * s->uinf_host.size(),
+                             hipMemcpyHostToDevice, s->stream));
+    return QL_OK;
+}
+
 int ql_init_freestream(ql_solver *s) {
     int st = ensure_ready(s, false);
     if (st) return st;
@@ -814,18 +847,7 @@ int ql_init_freestream(ql_solver *s) {
         s->case_mach[0] = s->prm.mach;
         s->case_alpha[0] = s->prm.alpha_deg;
     }
-    std::vector<double> uinf((size_t)4 * s->ncase);
-    for (int c = 0; c < s->ncase; ++c) {
-        const double a = s->case_alpha[c] * M_PI / 180.0;
-        const double rho = 1.0, u1 = s->case_mach[c] * std::cos(a), u2 = s->case_mach[c] * std::sin(a);
-        const double p = 1.0 / s->prm.gamma;
-        uinf[4 * c] = rho;
-        uinf[4 * c + 1] = rho * u1;
-        uinf[4 * c + 2] = rho * u2;
-        uinf[4 * c + 3] = p / (s->prm.gamma - 1.0) + 0.5 * rho * (u1 * u1 + u2 * u2);
-    }
-    HIPCHK(s, hipMemcpyAsync(s->uinf, uinf.data(), sizeof(double) * uinf.size(),
-                             hipMemcpyHostToDevice, s->stream));
+    if ((st = upload_freestream(s))) return st;
     HIPCHK(s, launch_freestream(s->stream, s->n, s->nrm, s->kind, s->case_of, s->uinf, s->U));
     st = prep_state(s);
     if (st) return st;
@@ -1018,6 +1040,107 @@ int ql_forces(ql_solver *s, double *cl, double *cd) {
     return case_forces(s, 0, cl, cd);
 }
 
+// --- warm start -------------------------------------------------------------
+
+// Stage-1 residual norms of the current U into row *wctr of s->wres, with
+// the error word left for the caller to read.
+static int warm_eval(ql_solver *s, const DevCloud &c, const FlowParams &fp) {
+    int st = prep_state(s);
+    if (st) return st;
+    if ((st = run_gradients(s, c, fp.limiter != 0))) return st;
+    if ((st = launch_stage(s, c, fp, 0, s->R))) return st;
+    HIPCHK(s, launch_resnorm(s->stream, s->R, s->n, s->nchunk, s->chunk_beg, s->part, s->ncase,
+                             s->chunk_ptr, s->inv_nupd, s->wctr, 2, s->wres));
+    return QL_OK;
+}
+
+int ql_wall_distance(ql_solver *s, double *d) {
+    int st = ensure_ready(s, false);
+    if (st) return st;
+    if (!d) return fail(s, QL_EINVAL, "output is NULL");
+    (void)hipSetDevice(s->device);
+    HIPCHK(s, launch_wall_distance(s->stream, s->n, s->xy, s->case_of, s->dwall_lo, s->wall,
+                                   s->tmp));
+    std::vector<double> h(s->n);
+    HIPCHK(s, hipMemcpyAsync(h.data(), s->tmp, sizeof(double) * s->n, hipMemcpyDeviceToHost,
+                             s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    for (int p = 0; p < s->n; ++p) d[s->perm[p]] = h[p];
+    return QL_OK;
+}
+
+int ql_warm_start(ql_solver *s, ql_mlp *m, const float *X, const float *out_scale,
+                  double rel_floor, double *res_cold, double *res_warm, int32_t *used) {
+    int st = ensure_ready(s, false);
+    if (st) return st;
+    if (!ql::mlp_ready(m)) return fail(s, QL_EINVAL, "the network is not usable (no weights?)");
+    if (!X || !out_scale) return fail(s, QL_EINVAL, "null features or output scale");
+    if (ql::mlp_width(m, 1) != 4)
+        return fail(s, QL_EINVAL, "the network must output 4 values (rho, u1, u2, p)");
+    if (!(rel_floor > 0.0 && rel_floor < 1.0)) return fail(s, QL_EINVAL, "floor must lie in (0, 1)");
+    (void)hipSetDevice(s->device);
+    const int n = s->n, nc = s->ncase;
+    if (s->ncase == 1) {
+        s->case_mach[0] = s->prm.mach;
+        s->case_alpha[0] = s->prm.alpha_deg;
+    }
+    // network output (caller order, FP32 [n][4]) into the residual buffer
+    float *Y = reinterpret_cast<float *>(s->R);
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    if ((st = ql_mlp_forward(m, X, Y, n)))
+        return fail(s, st, "network inference failed: %s", ql_mlp_last_error(m));
+    HIPCHK(s, hipStreamSynchronize(ql::mlp_stream(m)));
+    WarmScale sc;
+    for (int k = 0; k < 4; ++k) {
+        sc.mean[k] = out_scale[k];
+        sc.std[k] = out_scale[4 + k];
+    }
+    sc.floor = rel_floor;
+    if ((st = upload_freestream(s))) return st;
+    HIPCHK(s, launch_warm_state(s->stream, n, s->dperm, s->kind, s->nrm, s->case_of, s->uinf, Y,
+                                sc, s->prm.gamma, s->tmp));
+    const DevCloud c = dev_cloud(s);
+    const FlowParams fp = flow_params(s);
+    HIPCHK(s, hipMemcpyAsync(s->wctr, &s->zero, sizeof(int), hipMemcpyHostToDevice, s->stream));
+    // warm candidate: its stage-1 residual norms (row 0); a positivity or
+    // finiteness failure rejects the failing point's case
+    HIPCHK(s, hipMemcpyAsync(s->U, s->tmp, sizeof(double) * 4 * n, hipMemcpyDeviceToDevice,
+                             s->stream));
+    if ((st = warm_eval(s, c, fp))) return st;
+    int ew[2];
+    HIPCHK(s, hipMemcpyAsync(ew, s->errw, sizeof ew, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    int bad_case = -1;
+    if (ew[1] != kErrNone && ew[0] >= 0 && ew[0] < n) {
+        const int up = s->perm[ew[0]];
+        for (int k = 0; k < nc; ++k)
+            if (up >= s->case_lo[k] && up < s->case_lo[k + 1]) bad_case = k;
+    }
+    // cold start: freestream (row 1); failures here are errors
+    HIPCHK(s, launch_freestream(s->stream, n, s->nrm, s->kind, s->case_of, s->uinf, s->U));
+    if ((st = warm_eval(s, c, fp))) return st;
+    std::vector<double> rows((size_t)8 * nc);
+    HIPCHK(s, hipMemcpyAsync(rows.data(), s->wres, sizeof(double) * rows.size(),
+                             hipMemcpyDeviceToHost, s->stream));
+    if ((st = sync_and_check(s, "warm_start (freestream)"))) return st;
+    std::vector<uint8_t> sel(nc, 0);
+    for (int k = 0; k < nc; ++k) {
+        const double w = rows[4 * k], cold = rows[(size_t)4 * nc + 4 * k];
+        sel[k] = (k != bad_case && std::isfinite(w) && w <= cold) ? 1 : 0;
+        if (res_warm) std::copy(&rows[4 * k], &rows[4 * k] + 4, res_warm + 4 * k);
+        if (res_cold) std::copy(&rows[(size_t)4 * nc + 4 * k], &rows[(size_t)4 * nc + 4 * k] + 4,
+                                res_cold + 4 * k);
+        if (used) used[k] = sel[k];
+    }
+    HIPCHK(s, hipMemcpyAsync(s->wsel, sel.data(), nc, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, launch_select_state(s->stream, n, s->case_of, s->wsel, s->tmp, s->U));
+    if ((st = prep_state(s))) return st;
+    st = sync_and_check(s, "warm_start");
+    s->has_state = (st == QL_OK);
+    s->has_eval = s->has_res = false;
+    return st;
+}
+
 int ql_batch_forces(ql_solver *s, double *cl, double *cd) {
     int st = ensure_ready(s, true);
     if (st) return st;
@@ -1035,17 +1158,22 @@ int ql_batch_info(const ql_solver *s, int32_t *ncase) {
 }
 
 int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_every, int32_t graph,
-                 int32_t *iters_out, double *res_out) {
+                 const double *ref_res, int32_t *iters_out, double *res_out) {
     int st = ensure_ready(s, true);
     if (st) return st;
     if (!(drop > 0.0) || max_iter < 0 || check_every < 1)
         return fail(s, QL_EINVAL, "need drop > 0, max_iter >= 0, check_every >= 1");
+    if (ref_res)
+        for (int c = 0; c < s->ncase; ++c)
+            if (!(ref_res[c] > 0.0) || !std::isfinite(ref_res[c]))
+                return fail(s, QL_EINVAL, "reference residual of case %d must be > 0", c);
     (void)hipSetDevice(s->device);
     const int nc = s->ncase, ntile = num_flux_tiles(s->n);
     const int block = std::min(check_every, std::max(max_iter, 1));
     if ((st = ensure_history(s, block))) return st;
     std::vector<uint8_t> active(nc, 1), tile(ntile, 1);
     std::vector<double> ref(nc, -1.0), last((size_t)4 * nc, 0.0);
+    if (ref_res) ref.assign(ref_res, ref_res + nc);
     std::vector<int> iters(nc, 0);
     HIPCHK(s, hipMemcpyAsync(s->case_active, active.data(), nc, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemcpyAsync(s->tile_active, tile.data(), ntile, hipMemcpyHostToDevice, s->stream));

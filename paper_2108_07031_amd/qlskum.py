@@ -30,7 +30,10 @@ EXPORTS = ("ql_default_params", "ql_create", "ql_destroy", "ql_upload_cloud", "q
            "ql_fetch_state", "ql_forces", "ql_last_error", "ql_evaluate", "ql_debug_fetch",
            "ql_debug_flags", "ql_cloud_size", "ql_set_timing", "ql_kernel_time",
            "ql_batch_upload", "ql_batch_info", "ql_batch_run", "ql_batch_forces",
-           "ql_flux_tiles")
+           "ql_flux_tiles", "ql_mlp_create", "ql_mlp_destroy", "ql_mlp_last_error",
+           "ql_mlp_num_params", "ql_mlp_set_weights", "ql_mlp_get_weights", "ql_mlp_forward",
+           "ql_mlp_gradient", "ql_mlp_train_step", "ql_mlp_sync", "ql_wall_distance",
+           "ql_warm_start")
 
 
 class ql_params(C.Structure):
@@ -74,11 +77,24 @@ def _load():
     lib.ql_kernel_time.argtypes = [vp, i32, P(d), P(i64)]
     lib.ql_batch_upload.argtypes = [vp, i32, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.ql_batch_info.argtypes = [vp, P(i32)]
-    lib.ql_batch_run.argtypes = [vp, d, i32, i32, i32, vp, vp]
+    lib.ql_batch_run.argtypes = [vp, d, i32, i32, i32, vp, vp, vp]
     lib.ql_batch_forces.argtypes = [vp, vp, vp]
     lib.ql_flux_tiles.argtypes = [vp, P(i32), vp]
+    lib.ql_mlp_create.argtypes = [P(vp), i32, vp, vp, i32, i64]
+    lib.ql_mlp_destroy.argtypes = [vp]
+    lib.ql_mlp_last_error.argtypes = [vp]
+    lib.ql_mlp_last_error.restype = C.c_char_p
+    lib.ql_mlp_num_params.argtypes = [vp, P(i64)]
+    lib.ql_mlp_set_weights.argtypes = [vp, vp]
+    lib.ql_mlp_get_weights.argtypes = [vp, vp]
+    lib.ql_mlp_forward.argtypes = [vp, vp, vp, i64]
+    lib.ql_mlp_gradient.argtypes = [vp, vp, vp, i64, vp, P(d)]
+    lib.ql_mlp_train_step.argtypes = [vp, vp, vp, i64, C.c_float, P(d)]
+    lib.ql_mlp_sync.argtypes = [vp]
+    lib.ql_wall_distance.argtypes = [vp, vp]
+    lib.ql_warm_start.argtypes = [vp, vp, vp, vp, d, vp, vp, vp]
     for name in EXPORTS:
-        if name not in ("ql_default_params", "ql_last_error"):
+        if name not in ("ql_default_params", "ql_last_error", "ql_mlp_last_error"):
             getattr(lib, name).restype = C.c_int
     return lib
 
@@ -188,14 +204,170 @@ def ql_batch_upload(s, case_ptr, x, y, nx, ny, kind, nbr_ptr, nbr_idx, mach, alp
                                          *(k[1] for k in keep), m.ctypes.data, a.ctypes.data))
 
 
-def ql_batch_run(s, drop, max_iter, check_every=100, graph=True):
-    """Returns (iterations per case, last residual norms (ncase, 4))."""
+def ql_batch_run(s, drop, max_iter, check_every=100, graph=True, ref=None):
+    """Returns (iterations per case, last residual norms (ncase, 4)); ref:
+    per-case reference density-residual norms (None: first iteration's)."""
     nc = ql_batch_info(s)
     iters = np.zeros(nc, np.int32)
     res = np.zeros((nc, 4))
+    keep = None
+    if ref is not None:
+        keep = np.ascontiguousarray(ref, dtype=np.float64)
+        if keep.shape != (nc,):
+            raise ValueError("ref must hold one value per case")
     _check(s, lib.ql_batch_run(s, float(drop), int(max_iter), int(check_every), int(bool(graph)),
+                               keep.ctypes.data if keep is not None else None,
                                iters.ctypes.data, res.ctypes.data))
     return iters, res
+
+
+def ql_wall_distance(s):
+    n, _ = ql_cloud_size(s)
+    out = np.empty(n)
+    _check(s, lib.ql_wall_distance(s, out.ctypes.data))
+    return out
+
+
+def ql_warm_start(s, m, X, out_scale, rel_floor=0.05):
+    """X: device float32 tensor (n, w_in) in caller order; out_scale: 8
+    floats (mean[4], std[4]).  Returns (res_cold (ncase, 4), res_warm
+    (ncase, 4), used (ncase,) bool)."""
+    nc = ql_batch_info(s)
+    sc = np.ascontiguousarray(out_scale, dtype=np.float32)
+    if sc.shape != (8,):
+        raise ValueError("out_scale must hold 8 values")
+    rc, rw = np.zeros((nc, 4)), np.zeros((nc, 4))
+    used = np.zeros(nc, np.int32)
+    _check(s, lib.ql_warm_start(s, m, _dev_ptr(X), sc.ctypes.data, float(rel_floor),
+                                rc.ctypes.data, rw.ctypes.data, used.ctypes.data))
+    return rc, rw, used.astype(bool)
+
+
+# --- warm-start network --------------------------------------------------
+
+def _mcheck(m, rc):
+    if rc != QL_OK:
+        msg = lib.ql_mlp_last_error(m).decode() if m else ""
+        raise QLError(rc, msg)
+    return rc
+
+
+def ql_mlp_create(widths, max_batch, device=0, stream=None):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream(device).cuda_stream
+    elif not isinstance(stream, int):
+        stream = stream.cuda_stream
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    h = C.c_void_p()
+    rc = lib.ql_mlp_create(C.byref(h), int(device), C.c_void_p(stream) if stream else None,
+                           w.ctypes.data, int(w.size), int(max_batch))
+    if rc != QL_OK:
+        raise QLError(rc, "ql_mlp_create failed")
+    return h
+
+
+def ql_mlp_destroy(m):
+    return lib.ql_mlp_destroy(m)
+
+
+def ql_mlp_num_params(m):
+    n = C.c_int64()
+    _mcheck(m, lib.ql_mlp_num_params(m, C.byref(n)))
+    return n.value
+
+
+def ql_mlp_set_weights(m, w):
+    a = np.ascontiguousarray(w, dtype=np.float32)
+    if a.size != ql_mlp_num_params(m):
+        raise ValueError("weight vector has the wrong length")
+    return _mcheck(m, lib.ql_mlp_set_weights(m, a.ctypes.data))
+
+
+def ql_mlp_get_weights(m):
+    out = np.empty(ql_mlp_num_params(m), np.float32)
+    _mcheck(m, lib.ql_mlp_get_weights(m, out.ctypes.data))
+    return out
+
+
+def ql_mlp_forward(m, X, Y, n):
+    return _mcheck(m, lib.ql_mlp_forward(m, _dev_ptr(X), _dev_ptr(Y), int(n)))
+
+
+def ql_mlp_gradient(m, X, T, n):
+    """(loss, gradient as float32[np])."""
+    g = np.empty(ql_mlp_num_params(m), np.float32)
+    loss = C.c_double()
+    _mcheck(m, lib.ql_mlp_gradient(m, _dev_ptr(X), _dev_ptr(T), int(n), g.ctypes.data,
+                                   C.byref(loss)))
+    return loss.value, g
+
+
+def ql_mlp_train_step(m, X, T, n, lr, want_loss=True):
+    loss = C.c_double()
+    _mcheck(m, lib.ql_mlp_train_step(m, _dev_ptr(X), _dev_ptr(T), int(n), float(lr),
+                                     C.byref(loss) if want_loss else None))
+    return loss.value if want_loss else None
+
+
+def ql_mlp_sync(m):
+    return _mcheck(m, lib.ql_mlp_sync(m))
+
+
+class Mlp:
+    """Convenience owner of one network handle."""
+
+    def __init__(self, widths, max_batch, device=0, stream=None):
+        self.widths = list(widths)
+        self.h = ql_mlp_create(widths, max_batch, device, stream)
+
+    @property
+    def num_params(self):
+        return ql_mlp_num_params(self.h)
+
+    def set_weights(self, w):
+        ql_mlp_set_weights(self.h, w)
+
+    def get_weights(self):
+        return ql_mlp_get_weights(self.h)
+
+    def _rows(self, X, width):
+        import torch
+        if X.dtype != torch.float32 or X.dim() != 2 or X.shape[1] != width:
+            raise ValueError(f"expected a float32 (n, {width}) tensor")
+        return X.shape[0]
+
+    def forward(self, X, Y=None):
+        import torch
+        self._rows(X, self.widths[0])
+        if Y is None:
+            Y = torch.empty((X.shape[0], self.widths[-1]), dtype=torch.float32, device=X.device)
+        ql_mlp_forward(self.h, X, Y, X.shape[0])
+        ql_mlp_sync(self.h)
+        return Y
+
+    def gradient(self, X, T):
+        n = self._rows(X, self.widths[0])
+        if self._rows(T, self.widths[-1]) != n:
+            raise ValueError("X and T must have the same rows")
+        return ql_mlp_gradient(self.h, X, T, n)
+
+    def train_step(self, X, T, lr, want_loss=True):
+        n = self._rows(X, self.widths[0])
+        if self._rows(T, self.widths[-1]) != n:
+            raise ValueError("X and T must have the same rows")
+        return ql_mlp_train_step(self.h, X, T, n, lr, want_loss)
+
+    def close(self):
+        if self.h:
+            ql_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def ql_batch_forces(s):
@@ -314,8 +486,17 @@ class Solver:
                         ptr, idx, mach, alpha_deg)
         return offs
 
-    def batch_run(self, drop, max_iter, check_every=100, graph=True):
-        return ql_batch_run(self.h, drop, max_iter, check_every, graph)
+    def batch_run(self, drop, max_iter, check_every=100, graph=True, ref=None):
+        return ql_batch_run(self.h, drop, max_iter, check_every, graph, ref)
+
+    def wall_distance(self):
+        return ql_wall_distance(self.h)
+
+    def warm_start(self, mlp, X, out_scale, rel_floor=0.05):
+        n, _ = ql_cloud_size(self.h)
+        if mlp._rows(X, mlp.widths[0]) != n:
+            raise ValueError("one feature row per point is needed")
+        return ql_warm_start(self.h, mlp.h, X, out_scale, rel_floor)
 
     def batch_forces(self):
         return ql_batch_forces(self.h)

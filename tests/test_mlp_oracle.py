@@ -122,3 +122,25 @@ def test_training_reduces_the_loss():
         w, m, v = mlp.adam(w, g, m, v, t, 1e-2)
     l1, _ = mlp.loss_grad(w, widths, X, T)
     assert l1 < 0.05 * l0
+
+
+def test_bf16_gradient_is_exact_where_bf16_is_exact():
+    # one linear layer, small integers, n * w_out a power of two: every
+    # rounding in the emulated arithmetic is exact, so it equals FP64
+    rng = np.random.default_rng(9)
+    widths = [5, 4]
+    w = rng.integers(-8, 9, mlp.n_params(widths)).astype(np.float64)
+    X = rng.integers(-8, 9, (32, 5)).astype(np.float64)
+    _, y = mlp.forward(w, widths, X)
+    T = y - rng.integers(-4, 5, y.shape)
+    l, g = mlp.loss_grad(w, widths, X, T)
+    lb, gb = mlp.loss_grad_bf16(w, widths, X, T)
+    assert lb == l
+    np.testing.assert_array_equal(gb, g)
+
+
+def test_bf16_gradient_close_to_fp64():
+    w, X, T = _net(scale=0.4)
+    _, g = mlp.loss_grad(w, WIDTHS, X, T)
+    _, gb = mlp.loss_grad_bf16(w, WIDTHS, X, T)
+    assert np.max(np.abs(gb - g)) <= 0.03 * np.max(np.abs(g))
