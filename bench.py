@@ -12,6 +12,7 @@ Prints one JSON line (see the repository's measurement notes for the
 roofline and CPU-baseline definitions).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -34,6 +35,40 @@ PREC_NAME = {0: "fp64", 1: "mixed"}
 FLOPS_ENTRY_COMMON = 202       # geometry, reconstruction, two q~ -> primitive states
 FLOPS_ENTRY_LIMITER = 125      # Venkatakrishnan factors of 8 increments, eps^2
 FLOPS_PER_STENCIL = 191        # two split fluxes, their difference, weighted sum
+
+
+# HBM bytes of the flux kernel from committed rocprofv3 counters: the record
+# line of this file holds FETCH_SIZE / WRITE_SIZE (KiB per launch), the
+# calibration factors and the hash of the kernel sources it was taken with.
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "pmc_hbm_bytes_c2_fp64.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2108_07031_amd", "csrc", f) for f in
+                  ("qlskum_kernels.hip", "qlskum_internal.h", "qlskum_erfc.h",
+                   "qlskum_erfc_coeffs.h")]
+
+
+def kernel_sources_sha256():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic():
+    """Bytes per flux launch, or None when the record is missing or was
+    taken with other kernel sources."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            for line in fh:
+                if line.startswith("record: "):
+                    rec = json.loads(line[len("record: "):])
+                    if rec.get("sources_sha256") != kernel_sources_sha256():
+                        return None
+                    return (rec["fetch_kib"] * 1024.0 * rec["fetch_scale"] +
+                            rec["write_kib"] * 1024.0 * rec["write_scale"])
+    except (OSError, ValueError, KeyError):
+        return None
+    return None
 
 
 def log(msg):
@@ -71,12 +106,122 @@ def cpu_baseline(cloud, seconds_hint=30.0):
                       f"({t:.1f} s single-threaded); iteration = 4 stages"}
 
 
+# Learned warm start (time to a 1e-6 residual drop, warm vs cold) on small
+# clouds: training conditions converged in one batched run, a network
+# 6 -> 4 x 128 (tanh) -> 4 trained on their converged primitive fields, then
+# held-out conditions solved cold and warm, one at a time.
+WARM = dict(ns=64, nr=24, n_train=24, n_test=8, seed_train=1, seed_test=2, drop=1e-6,
+            max_iter=40000, widths=[6, 128, 128, 128, 128, 4], steps=2000, batch=8192,
+            lr=2e-3, floor=0.05)
+
+
+def _prims(U, gamma=1.4):
+    rho = U[0]
+    u, v = U[1] / rho, U[2] / rho
+    return np.stack([rho, u, v, (gamma - 1.0) * (U[3] - 0.5 * rho * (u * u + v * v))], axis=1)
+
+
+def warm_study():
+    import torch
+    from cloudgen import (glorot_weights, naca_ocloud, sample_conditions, uniform01,
+                          warm_features)
+    from paper_2108_07031_amd import qlskum as ql
+    W = WARM
+    t_all = time.perf_counter()
+    train = sample_conditions(W["seed_train"], W["n_train"])
+    test = sample_conditions(W["seed_test"], W["n_test"])
+    cloud_of = lambda c: naca_ocloud(W["ns"], W["nr"], tau=c["tau"])
+    clouds = [cloud_of(c) for c in train]
+    # 1. converge the training conditions together
+    s = ql.Solver(limiter=1)
+    offs = s.upload_batch(clouds, [c["mach"] for c in train], [c["alpha"] for c in train])
+    s.init_freestream()
+    t0 = time.perf_counter()
+    it_train, _ = s.batch_run(W["drop"], W["max_iter"], check_every=500)
+    t_conv = time.perf_counter() - t0
+    U = s.fetch_state()
+    d = s.wall_distance()
+    s.close()
+    F = np.concatenate([warm_features(cl, d[offs[i]:offs[i + 1]], c["mach"], c["alpha"],
+                                      c["tau"]) for i, (cl, c) in enumerate(zip(clouds, train))])
+    keep = np.concatenate([cl.kind for cl in clouds]) != 2
+    F, P = F[keep], _prims(U)[keep]
+    fm, fs = F.mean(axis=0), F.std(axis=0) + 1e-12
+    pm, ps = P.mean(axis=0), P.std(axis=0) + 1e-12
+    X = torch.tensor((F - fm) / fs, dtype=torch.float32, device="cuda")
+    Y = torch.tensor((P - pm) / ps, dtype=torch.float32, device="cuda")
+    # 2. train (minibatches from a seeded shuffle of the samples)
+    m = ql.Mlp(W["widths"], max_batch=W["batch"])
+    m.set_weights(glorot_weights(W["widths"], 2108))
+    nb = X.shape[0] // W["batch"]
+    order = torch.tensor(np.argsort(uniform01(31, X.shape[0] * 64).reshape(64, -1), axis=1),
+                         device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = None
+    for step in range(W["steps"]):
+        ep, b = divmod(step, max(nb, 1))
+        idx = order[ep % 64, b * W["batch"]:(b + 1) * W["batch"]]
+        lr = W["lr"] * (0.1 if step >= 0.75 * W["steps"] else 1.0)
+        loss = m.train_step(X[idx].contiguous(), Y[idx].contiguous(), lr,
+                            want_loss=(step == W["steps"] - 1))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    # 3. held-out conditions, cold and warm
+    rows = []
+    for c in test:
+        cl = cloud_of(c)
+        prm = dict(limiter=1, mach=c["mach"], alpha_deg=c["alpha"])
+        sc = ql.Solver(cl, **prm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sc.init_freestream()
+        ic, rc_last = sc.batch_run(W["drop"], W["max_iter"], check_every=100)
+        t_cold = time.perf_counter() - t0
+        dw = sc.wall_distance()
+        sc.close()
+        sw = ql.Solver(cl, **prm)
+        Xc = torch.tensor((warm_features(cl, dw, c["mach"], c["alpha"], c["tau"]) - fm) / fs,
+                          dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rcold, rwarm, used = sw.warm_start(m, Xc, np.concatenate([pm, ps]), W["floor"])
+        iw, _ = sw.batch_run(W["drop"], W["max_iter"], check_every=100, ref=rcold[:, 0])
+        t_warm = time.perf_counter() - t0
+        sw.close()
+        rows.append(dict(iters_cold=int(ic[0]), iters_warm=int(iw[0]), t_cold=t_cold,
+                         t_warm=t_warm, used=bool(used[0]),
+                         r1_ratio=float(rwarm[0, 0] / rcold[0, 0])))
+        log(f"warm study: M {c['mach']:.3f} alpha {c['alpha']:.2f} tau {c['tau']:.3f}: "
+            f"cold {ic[0]} its {t_cold:.2f} s, warm {iw[0]} its {t_warm:.2f} s, "
+            f"R1 warm/cold {rows[-1]['r1_ratio']:.3f}, used {bool(used[0])}")
+    m.close()
+    ratio = [r["t_warm"] / r["t_cold"] for r in rows]
+    return {
+        "cases_train": W["n_train"], "cases_test": W["n_test"],
+        "points_per_case": W["ns"] * W["nr"],
+        "drop": W["drop"], "max_iter": W["max_iter"],
+        "train_converged": int(np.sum(np.asarray(it_train) < W["max_iter"])),
+        "train_solve_s": t_conv, "train_net_s": t_train, "train_loss": loss,
+        "network": "6-128x4-4 tanh, bf16 MFMA, FP32 accumulate, Adam",
+        "iters_cold": [r["iters_cold"] for r in rows],
+        "iters_warm": [r["iters_warm"] for r in rows],
+        "time_ratio_median": float(np.median(ratio)),
+        "iters_ratio_median": float(np.median([r["iters_warm"] / r["iters_cold"]
+                                                for r in rows])),
+        "fallbacks": int(sum(not r["used"] for r in rows)),
+        "r1_warm_over_cold": [r["r1_ratio"] for r in rows],
+        "study_s": time.perf_counter() - t_all,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-warm-study", action="store_true")
     ap.add_argument("--precision", choices=("both", "fp64", "mixed"), default="both")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference kernel for "
@@ -174,7 +319,7 @@ def main():
             "peak": FP64_VALU_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_VALU_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": committed_traffic(),
             "flops_per_launch": flops,
             "avg_launch_us": flux_avg_s * 1e6,
         },
@@ -186,6 +331,12 @@ def main():
                         "ms_per_step": runs[1]["elapsed"] * 1e3 / args.steps,
                         "over_fp64": runs[1]["value"] / runs[0]["value"],
                         "dtype": "f32 flux body, f64 sums and update"}
+    if not args.no_warm_study:
+        log("warm-start study")
+        try:
+            out["warm_start"] = warm_study()
+        except Exception as e:  # reported, never hides the throughput line
+            out["warm_start"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one stage of the full cloud)")
         out["cpu_baseline"] = cpu_baseline(cloud)

@@ -78,6 +78,8 @@ typedef struct {
                          the records of its 64-point tile and halo (tiles that
                          do not fit read from memory; same results either
                          way); 0 = the library's default, at most 163840      */
+    int32_t grad_lds; /* tuning: the same for the q-derivative sweeps (records
+                         of 48 and 80 bytes); 0 = default, at most 163840     */
 } ql_params;
 
 /* Fill *p with the defaults: gamma 1.4, M 0.63, alpha 2, CFL 0.2, 3 inner
@@ -210,8 +212,9 @@ int ql_batch_forces(ql_solver *s, double *cl, double *cd);
  * accumulation; bias, tanh, loss and Adam in FP32).  The initial state of
  * an explicit solve is arbitrary; a network that maps point features
  * (position, wall distance, flow condition) to the converged primitive
- * fields gives a start closer to the solution (spec item: learned
- * warm start).  The network object is separate from the solver; max_batch
+ * fields gives a start closer to the solution (the paper's method starts
+ * from the freestream; this is an addition to it).  The network object is
+ * separate from the solver; max_batch
  * bounds the rows of one training step (inference is chunked).  The
  * library owns all device buffers; hip_stream as in ql_create.
  * Weights are one FP32 vector: for each layer l, W_l row-major
@@ -284,6 +287,19 @@ int ql_evaluate(ql_solver *s);
  * bytes (FP64 with limiter), 112 (FP64), 96 (mixed with limiter) or 64
  * (mixed).  Errors: QL_EINVAL (NULL), QL_ESTATE (no cloud). */
 int ql_flux_tiles(const ql_solver *s, int32_t *ntile, int32_t *slots);
+
+/* Autotuning of the tiled sweeps: times the flux sweep (stage evaluation)
+ * and the q-derivative sweeps of the current state for a set of LDS
+ * budgets and keeps the fastest in flux_lds and grad_lds.  Results do not
+ * depend on the budgets (tiles that do not fit read from memory with the
+ * same arithmetic), so tuning never changes an answer.  When cache_path is
+ * not NULL the choice is looked up there first, keyed by precision,
+ * limiter, size class (log2 n) and mean stencil size, and stored there
+ * after tuning (a small JSON object, one entry per line).  chosen[2]
+ * (nullable) receives (flux_lds, grad_lds).  The state is not changed.
+ * Errors: QL_ESTATE (no state), QL_EINVAL (unreadable or unwritable cache
+ * file), device errors. */
+int ql_autotune(ql_solver *s, const char *cache_path, int32_t *chosen);
 
 /* Copy an inspection array to host memory `out` in caller order:
  *   0 q [4][n]       1 g [8][n] (q_x rows 0..3, q_y rows 4..7)

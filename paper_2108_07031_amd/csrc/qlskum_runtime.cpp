@@ -299,6 +299,8 @@ int check_params(ql_solver *s, const ql_params *p) {
     if (p->reorder != 0 && p->reorder != 1) return fail(s, QL_EINVAL, "reorder must be 0 or 1");
     if (p->flux_lds < 0 || p->flux_lds > 160 * 1024)
         return fail(s, QL_EINVAL, "flux_lds must lie in [0, 163840] bytes");
+    if (p->grad_lds < 0 || p->grad_lds > 160 * 1024)
+        return fail(s, QL_EINVAL, "grad_lds must lie in [0, 163840] bytes");
     return QL_OK;
 }
 
@@ -394,7 +396,8 @@ int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds) {
     }
     {
         Timer t(s, 0);
-        HIPCHK(s, launch_grad0(s->stream, c, kGrad0Lds, s->q[s->qcur], s->g[first], s->qmm,
+        HIPCHK(s, launch_grad0(s->stream, c, s->prm.grad_lds > 0 ? s->prm.grad_lds : kGrad0Lds,
+                               s->q[s->qcur], s->g[first], s->qmm,
                                want_bounds ? 1 : 0, sh));
         t.done();
     }
@@ -403,7 +406,8 @@ int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds) {
         const int nxt = (cur == 0) ? 1 : 0;
         float4 *g32 = (mixed && k == s->prm.n_inner - 1) ? s->g32 : nullptr;
         Timer t(s, 1);
-        HIPCHK(s, launch_gradk(s->stream, c, kGradkLds, s->g[2], s->g[cur], s->g[nxt], g32));
+        HIPCHK(s, launch_gradk(s->stream, c, s->prm.grad_lds > 0 ? s->prm.grad_lds : kGradkLds,
+                               s->g[2], s->g[cur], s->g[nxt], g32));
         t.done();
         cur = nxt;
     }
@@ -539,6 +543,7 @@ void ql_default_params(ql_params *p) {
     p->precision = 0;
     p->reorder = 1;
     p->flux_lds = 0;
+    p->grad_lds = 0;
 }
 
 int ql_create(ql_solver **out, int32_t device, void *hip_stream) {
@@ -1139,6 +1144,149 @@ int ql_warm_start(ql_solver *s, ql_mlp *m, const float *X, const float *out_scal
     s->has_state = (st == QL_OK);
     s->has_eval = s->has_res = false;
     return st;
+}
+
+// --- autotuning of the LDS budgets ------------------------------------------
+
+static std::string tune_key(const ql_solver *s) {
+    char buf[128];
+    const int lg = (int)std::lround(std::log2((double)std::max(s->n, 1)));
+    const int kbar = (int)std::lround((double)s->nnz / std::max(s->n, 1));
+    std::snprintf(buf, sizeof buf, "%s/lim%d/n2^%d/k%d", s->prm.precision ? "mixed" : "fp64",
+                  s->prm.limiter, lg, kbar);
+    return buf;
+}
+
+// entry lines of a cache file: "key": {"flux_lds": F, "grad_lds": G, ...}
+static bool cache_lookup(const char *path, const std::string &key, int *f, int *g) {
+    FILE *fp = std::fopen(path, "r");
+    if (!fp) return false;
+    char line[512];
+    bool found = false;
+    const std::string head = "\"" + key + "\":";
+    while (!found && std::fgets(line, sizeof line, fp)) {
+        const char *p = std::strstr(line, head.c_str());
+        if (!p) continue;
+        const char *a = std::strstr(p, "\"flux_lds\":"), *b = std::strstr(p, "\"grad_lds\":");
+        if (a && b && std::sscanf(a + 11, "%d", f) == 1 && std::sscanf(b + 11, "%d", g) == 1)
+            found = true;
+    }
+    std::fclose(fp);
+    return found;
+}
+
+static bool cache_store(const char *path, const std::string &key, const std::string &entry) {
+    std::vector<std::string> keep;
+    if (FILE *fp = std::fopen(path, "r")) {
+        char line[512];
+        const std::string head = "\"" + key + "\":";
+        while (std::fgets(line, sizeof line, fp)) {
+            std::string l(line);
+            while (!l.empty() && (l.back() == '\n' || l.back() == ',' || l.back() == ' ')) l.pop_back();
+            if (l.empty() || l == "{" || l == "}" || l.find(head) != std::string::npos) continue;
+            keep.push_back(l);
+        }
+        std::fclose(fp);
+    }
+    keep.push_back(entry);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *fp = std::fopen(tmp.c_str(), "w");
+    if (!fp) return false;
+    std::fprintf(fp, "{\n");
+    for (size_t i = 0; i < keep.size(); ++i)
+        std::fprintf(fp, "%s%s\n", keep[i].c_str(), i + 1 < keep.size() ? "," : "");
+    std::fprintf(fp, "}\n");
+    const bool ok = std::fclose(fp) == 0;
+    return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+int ql_autotune(ql_solver *s, const char *cache_path, int32_t *chosen) {
+    int st = ensure_ready(s, true);
+    if (st) return st;
+    (void)hipSetDevice(s->device);
+    const std::string key = tune_key(s);
+    int bf = 0, bg = 0;
+    if (cache_path && cache_lookup(cache_path, key, &bf, &bg)) {
+        ql_params p = s->prm;
+        p.flux_lds = bf;
+        p.grad_lds = bg;
+        if ((st = ql_set_params(s, &p))) return st;
+        if (chosen) {
+            chosen[0] = bf;
+            chosen[1] = bg;
+        }
+        return QL_OK;
+    }
+    const DevCloud c = dev_cloud(s);
+    const FlowParams fp = flow_params(s);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(s, hipEventCreate(&e0));
+    HIPCHK(s, hipEventCreate(&e1));
+    const bool was_timing = s->timing;
+    s->timing = false;
+    auto timed = [&](auto &&enqueue, int reps, double *us) -> int {
+        int r = enqueue();  // warm-up
+        if (r) return r;
+        HIPCHK(s, hipEventRecord(e0, s->stream));
+        for (int k = 0; k < reps; ++k)
+            if ((r = enqueue())) return r;
+        HIPCHK(s, hipEventRecord(e1, s->stream));
+        HIPCHK(s, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPCHK(s, hipEventElapsedTime(&ms, e0, e1));
+        *us = 1e3 * ms / reps;
+        return QL_OK;
+    };
+    const int flux_c[] = {16, 24 << 10, 32 << 10, 40 << 10, 48 << 10, 52 << 10, 64 << 10, 80 << 10};
+    const int grad_c[] = {16, 16 << 10, 24 << 10, 32 << 10, 40 << 10, 48 << 10};
+    const ql_params saved = s->prm;
+    double best_f = 1e30, best_g = 1e30, us = 0.0;
+    if ((st = reset_err(s)) || (st = prep_state(s)) || (st = run_gradients(s, c, fp.limiter != 0)))
+        goto done;
+    for (int b : flux_c) {
+        s->prm.flux_lds = b;
+        if ((st = timed([&] { return launch_stage(s, c, fp, 0, s->R); }, 5, &us))) goto done;
+        if (us < best_f) {
+            best_f = us;
+            bf = b;
+        }
+    }
+    s->prm.flux_lds = saved.flux_lds;
+    for (int b : grad_c) {
+        s->prm.grad_lds = b;
+        if ((st = timed([&] { return run_gradients(s, c, fp.limiter != 0); }, 3, &us))) goto done;
+        if (us < best_g) {
+            best_g = us;
+            bg = b;
+        }
+    }
+done:
+    s->prm = saved;
+    s->timing = was_timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    if ((st = sync_and_check(s, "autotune"))) return st;
+    s->has_eval = false;
+    s->prm.flux_lds = bf;
+    s->prm.grad_lds = bg;
+    s->graph_qcur = -1;  // a captured iteration holds the old budgets
+    if (s->graph) (void)hipGraphExecDestroy(s->graph);
+    s->graph = nullptr;
+    if (chosen) {
+        chosen[0] = bf;
+        chosen[1] = bg;
+    }
+    if (cache_path) {
+        char entry[256];
+        std::snprintf(entry, sizeof entry,
+                      "\"%s\": {\"flux_lds\": %d, \"grad_lds\": %d, \"flux_us\": %.1f, "
+                      "\"grad_us\": %.1f}",
+                      key.c_str(), bf, bg, best_f, best_g);
+        if (!cache_store(cache_path, key, entry))
+            return fail(s, QL_EINVAL, "cannot write the tuning cache %s", cache_path);
+    }
+    return QL_OK;
 }
 
 int ql_batch_forces(ql_solver *s, double *cl, double *cd) {

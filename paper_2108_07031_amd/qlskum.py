@@ -33,14 +33,14 @@ EXPORTS = ("ql_default_params", "ql_create", "ql_destroy", "ql_upload_cloud", "q
            "ql_flux_tiles", "ql_mlp_create", "ql_mlp_destroy", "ql_mlp_last_error",
            "ql_mlp_num_params", "ql_mlp_set_weights", "ql_mlp_get_weights", "ql_mlp_forward",
            "ql_mlp_gradient", "ql_mlp_train_step", "ql_mlp_sync", "ql_wall_distance",
-           "ql_warm_start")
+           "ql_warm_start", "ql_autotune")
 
 
 class ql_params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("mach", C.c_double), ("alpha_deg", C.c_double),
                 ("cfl", C.c_double), ("n_inner", C.c_int32), ("limiter", C.c_int32),
                 ("venkat_k", C.c_double), ("precision", C.c_int32), ("reorder", C.c_int32),
-                ("flux_lds", C.c_int32)]
+                ("flux_lds", C.c_int32), ("grad_lds", C.c_int32)]
 
 
 class QLError(RuntimeError):
@@ -93,6 +93,7 @@ def _load():
     lib.ql_mlp_sync.argtypes = [vp]
     lib.ql_wall_distance.argtypes = [vp, vp]
     lib.ql_warm_start.argtypes = [vp, vp, vp, vp, d, vp, vp, vp]
+    lib.ql_autotune.argtypes = [vp, C.c_char_p, vp]
     for name in EXPORTS:
         if name not in ("ql_default_params", "ql_last_error", "ql_mlp_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -219,6 +220,14 @@ def ql_batch_run(s, drop, max_iter, check_every=100, graph=True, ref=None):
                                keep.ctypes.data if keep is not None else None,
                                iters.ctypes.data, res.ctypes.data))
     return iters, res
+
+
+def ql_autotune(s, cache_path=None):
+    """Tune the LDS budgets on the current state; returns (flux_lds, grad_lds)."""
+    out = np.zeros(2, np.int32)
+    _check(s, lib.ql_autotune(s, cache_path.encode() if cache_path else None,
+                              out.ctypes.data))
+    return int(out[0]), int(out[1])
 
 
 def ql_wall_distance(s):
@@ -491,6 +500,9 @@ class Solver:
 
     def wall_distance(self):
         return ql_wall_distance(self.h)
+
+    def autotune(self, cache_path=None):
+        return ql_autotune(self.h, cache_path)
 
     def warm_start(self, mlp, X, out_scale, rel_floor=0.05):
         n, _ = ql_cloud_size(self.h)

@@ -37,6 +37,7 @@ def test_host_side_checks_without_gpu():
 
 def test_params_struct_layout():
     from paper_2108_07031_amd import qlskum as q
-    # doubles and int32s as in the header: 4 d, 2 i32, 1 d, 3 i32, padded to 8
-    assert C.sizeof(q.ql_params) == 4 * 8 + 2 * 4 + 8 + 3 * 4 + 4
+    # doubles and int32s as in the header: 4 d, 2 i32, 1 d, 4 i32
+    assert C.sizeof(q.ql_params) == 4 * 8 + 2 * 4 + 8 + 4 * 4
     assert q.ql_params.flux_lds.offset == 4 * 8 + 2 * 4 + 8 + 2 * 4
+    assert q.ql_params.grad_lds.offset == 4 * 8 + 2 * 4 + 8 + 3 * 4

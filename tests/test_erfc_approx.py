@@ -25,6 +25,7 @@ def erfc_exe(tmp_path_factory):
 
 def test_erfc_accuracy(erfc_exe):
     ys = np.concatenate([np.linspace(-6, 6, 2401), np.linspace(-1e-3, 1e-3, 41),
+                         np.linspace(-1.001, 1.001, 801), [np.nextafter(1.0, 2.0), -np.nextafter(1.0, 2.0)],
                          [-30.0, -10.0, 8.0, 10.0, 20.0, 26.0, 0.0]])
     out = subprocess.run([erfc_exe], input="\n".join(repr(float(v)) for v in ys),
                          capture_output=True, text=True, check=True).stdout.split()

@@ -1,4 +1,4 @@
-"""The flux sweep's LDS staging changes where records are read from, never
+"""The tiled sweeps' LDS staging changes where records are read from, never
 the arithmetic: every point's residual is summed over its entries in one
 fixed order whether its tile's image sits in LDS or is read from memory, so
 results are bitwise identical across LDS budgets (all tiles staged, none
@@ -49,7 +49,9 @@ def test_flux_lds_budget_invariance(ql, precision, limiter):
     assert all(0.0 < f < 1.0 for f in staged)
     out = []
     for b in budgets:
-        s = ql.Solver(c, precision=precision, limiter=limiter, flux_lds=b, **flow)
+        # the no-staging run also reads every q-derivative record from memory
+        s = ql.Solver(c, precision=precision, limiter=limiter, flux_lds=b,
+                      grad_lds=16 if b == 16 else 0, **flow)
         s.set_state(U0)
         R = s.evaluate()["R"]
         s.set_state(U0)
@@ -70,3 +72,30 @@ def test_flux_lds_budget_rejected(ql):
     with pytest.raises(ql.QLError):
         s.set_params(flux_lds=200 * 1024)
     s.close()
+
+
+def test_autotune_keeps_results_and_caches(ql, tmp_path):
+    _say("autotune")
+    c = cloud("jitter")
+    U0 = smooth_state(c, mach=0.85, alpha_deg=1.0)
+    prm = dict(precision=0, limiter=1, mach=0.85, alpha_deg=1.0)
+    s = ql.Solver(c, **prm)
+    s.set_state(U0)
+    h0 = s.step(10)
+    U1 = s.fetch_state()
+    s.set_state(U0)
+    cache = str(tmp_path / "tune.json")
+    f, g = s.autotune(cache)
+    _say(f"  chosen flux_lds {f}, grad_lds {g}")
+    assert 0 < f <= 163840 and 0 < g <= 163840
+    h1 = s.step(10)
+    np.testing.assert_array_equal(h1, h0)
+    np.testing.assert_array_equal(s.fetch_state(), U1)
+    s.close()
+    import json
+    entries = json.load(open(cache))
+    assert len(entries) == 1 and list(entries.values())[0]["flux_lds"] == f
+    s2 = ql.Solver(c, **prm)
+    s2.set_state(U0)
+    assert s2.autotune(cache) == (f, g)  # read back, not re-tuned
+    s2.close()
