@@ -47,7 +47,7 @@ class OracleError(RuntimeError):
 class _Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("mach", C.c_double), ("alpha_deg", C.c_double),
                 ("cfl", C.c_double), ("n_inner", C.c_int32), ("limiter", C.c_int32),
-                ("venkat_k", C.c_double)]
+                ("venkat_k", C.c_double), ("order", C.c_int32)]
 
 
 class _Cloud(C.Structure):
@@ -95,9 +95,12 @@ def _p(a):
     return a.ctypes.data if a is not None else None
 
 
-def params(gamma=1.4, mach=0.63, alpha_deg=2.0, cfl=0.2, n_inner=3, limiter=0, venkat_k=5.0):
+def params(gamma=1.4, mach=0.63, alpha_deg=2.0, cfl=0.2, n_inner=3, limiter=0, venkat_k=5.0,
+           order=2):
+    """order 2: modified q of eq. (28) (second order); 1: first-order LSKUM,
+    the split fluxes of q itself."""
     return dict(gamma=gamma, mach=mach, alpha_deg=alpha_deg, cfl=cfl, n_inner=n_inner,
-                limiter=limiter, venkat_k=venkat_k)
+                limiter=limiter, venkat_k=venkat_k, order=order)
 
 
 class Oracle:

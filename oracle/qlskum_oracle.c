@@ -55,6 +55,7 @@ typedef struct {
     double gamma, mach, alpha_deg, cfl;
     int32_t n_inner, limiter;
     double venkat_k;
+    int32_t order; /* 2: modified q of eq. (28); 1: first order, q~ = q */
 } ora_params;
 
 typedef struct {
@@ -437,6 +438,11 @@ int ora_flux_residual(const ora_cloud *cl, const ora_params *prm, const double *
             }
             double qti[4], qt0[4];
             for (int r = 0; r < 4; ++r) {
+                if (prm->order == 1) { /* first-order LSKUM: split fluxes of q itself */
+                    qti[r] = q[r * n + i];
+                    qt0[r] = q[r * n + p];
+                    continue;
+                }
                 double di = -0.5 * (dx * g[r * n + i] + dy * g[(4 + r) * n + i]);
                 double d0 = -0.5 * (dx * g[r * n + p] + dy * g[(4 + r) * n + p]);
                 double phii = 1.0, phi0 = 1.0;

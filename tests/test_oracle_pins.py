@@ -232,11 +232,11 @@ def _exact_divergence(x, y, mach=0.6, amp=0.08):
     return U, div
 
 
-def _consistency_errors(n_inner, levels=((24, 0.08), (48, 0.04))):
+def _consistency_errors(n_inner, levels=((24, 0.08), (48, 0.04)), order=2):
     errs = []
     for n, h in levels:
         c = _periodic_lattice(n, h, 0.15, seed=7)
-        o = oracle.Oracle(c, oracle.params(limiter=0, n_inner=n_inner))
+        o = oracle.Oracle(c, oracle.params(limiter=0, n_inner=n_inner, order=order))
         o.require_valid()
         U, div = _exact_divergence(c.x, c.y)
         R = o.evaluate(U)["R"]
@@ -255,6 +255,20 @@ def test_residual_consistent_second_order(oracle_lib):
     assert e2[0] / e2[1] > 3.6, e2
     e1 = _consistency_errors(0)
     assert 1.7 < e1[0] / e1[1] < 2.6, e1
+
+
+def test_first_order_mode_consistent_first_order(oracle_lib):
+    """First-order LSKUM (the split-flux derivatives of eqs. (12)-(14) applied
+    to the fluxes of q itself, no modified q): the residual converges to the
+    flux divergence at first order, and no q-derivative enters it."""
+    e = _consistency_errors(0, order=1)
+    assert e[0] < 0.3  # 0.24 at h = 0.08, 0.127 at 0.04, 0.066 at 0.02
+    assert 1.7 < e[0] / e[1] < 2.3, e
+    c = _periodic_lattice(24, 0.08, 0.15, seed=7)
+    U, _ = _exact_divergence(c.x, c.y)
+    R0 = oracle.Oracle(c, oracle.params(n_inner=0, order=1)).evaluate(U)["R"]
+    R3 = oracle.Oracle(c, oracle.params(n_inner=3, order=1)).evaluate(U)["R"]
+    np.testing.assert_array_equal(R0, R3)
 
 
 def test_rotation_invariance(oracle_lib):
@@ -339,7 +353,7 @@ def test_singular_stencil_is_rejected(oracle_lib):
 
 
 # ---------------------------------------------------------------- brute force
-def _five_point_bruteforce(c, U, limiter, n_inner=3, K=5.0, dps=30):
+def _five_point_bruteforce(c, U, limiter, n_inner=3, K=5.0, dps=30, order=2):
     """Independent evaluation of the stage operator at P0 of the five-point
     cloud in 30-digit arithmetic: q from eq. (26); q-derivatives by QR least
     squares of eq. (11) and of the defect-corrected differences of eq. (29)
@@ -376,6 +390,8 @@ def _five_point_bruteforce(c, U, limiter, n_inner=3, K=5.0, dps=30):
     qmin = [[min([q[p][r]] + [q[i][r] for i in nbrs[p]]) for r in range(4)] for p in range(n)]
 
     def recon(p, dx, dy, r, eps2):
+        if order == 1:
+            return q[p][r]
         d = -(dx * g[p][r][0] + dy * g[p][r][1]) / 2
         if not limiter:
             return q[p][r] + d
@@ -434,19 +450,20 @@ def _five_point_bruteforce(c, U, limiter, n_inner=3, K=5.0, dps=30):
     return gout, R, np.array(parts)
 
 
-@pytest.mark.parametrize("limiter", [0, 1])
-def test_five_point_bruteforce(oracle_lib, limiter):
+@pytest.mark.parametrize("limiter,order", [(0, 2), (1, 2), (0, 1)])
+def test_five_point_bruteforce(oracle_lib, limiter, order):
     """Five points, complete connectivity, global frame; P1..P4 supply
     neighbours only.  Oracle g (all points) and R (P0) against the
-    independent 30-digit evaluation above."""
+    independent 30-digit evaluation above (second order with and without
+    the limiter, and first order)."""
     from cloudgen import five_point_cloud
     c = five_point_cloud(0.05)
     c.kind[1:] = 2
-    o = oracle.Oracle(c, oracle.params(limiter=limiter, n_inner=3, venkat_k=5.0))
+    o = oracle.Oracle(c, oracle.params(limiter=limiter, n_inner=3, venkat_k=5.0, order=order))
     o.require_valid()
     U = smooth_state(c, amp=0.3)
     ev = o.evaluate(U)
-    g_bf, R_bf, parts = _five_point_bruteforce(c, U, limiter)
+    g_bf, R_bf, parts = _five_point_bruteforce(c, U, limiter, order=order)
     assert np.abs(ev["g"] - g_bf).max() <= 1e-13 * np.abs(g_bf).max()
     scale = np.abs(parts).max()
     assert np.abs(ev["R"][:, 0] - R_bf).max() <= 1e-13 * scale, (ev["R"][:, 0], R_bf)
