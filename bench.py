@@ -110,9 +110,58 @@ def cpu_baseline(cloud, seconds_hint=30.0):
 # clouds: training conditions converged in one batched run, a network
 # 6 -> 4 x 128 (tanh) -> 4 trained on their converged primitive fields, then
 # held-out conditions solved cold and warm, one at a time.
-WARM = dict(ns=64, nr=24, n_train=24, n_test=8, seed_train=1, seed_test=2, drop=1e-6,
-            max_iter=40000, widths=[6, 128, 128, 128, 128, 4], steps=2000, batch=8192,
+WARM = dict(ns=64, nr=24, n_train=48, n_test=8, seed_train=1, seed_test=2, drop=1e-6,
+            max_iter=40000, widths=[6, 128, 128, 128, 128, 4], steps=8000, batch=8192,
             lr=2e-3, floor=0.05)
+
+
+# Batched form: independent clouds of log-uniform sizes advanced by the same
+# launches (one captured iteration replayed), against the same clouds run
+# one after the other.
+BATCH = dict(n_case=16, n_lo=20000, n_hi=160000, seed=7031, iters=200)
+
+
+def batch_study():
+    import torch
+    from cloudgen import naca_ocloud, sample_conditions, uniform01
+    from paper_2108_07031_amd import qlskum as ql
+    B = BATCH
+    u = uniform01(B["seed"], B["n_case"])
+    sizes = np.exp(np.log(B["n_lo"]) + u * (np.log(B["n_hi"]) - np.log(B["n_lo"])))
+    conds = sample_conditions(B["seed"] + 1, B["n_case"], mach=(0.3, 0.85))
+    clouds = []
+    for k, (nn, c) in enumerate(zip(sizes, conds)):
+        ns = 2 * int(round(np.sqrt(5.0 * nn / 8.0) / 2))  # Ns:Nr = 5:8, Ns even
+        clouds.append(naca_ocloud(ns, int(round(nn / ns)), tau=c["tau"], jitter=0.1,
+                                  seed=B["seed"] + 10 + k))
+    total = sum(cl.n for cl in clouds)
+    prm = dict(limiter=1)
+    s = ql.Solver(**prm)
+    s.upload_batch(clouds, [c["mach"] for c in conds], [c["alpha"] for c in conds])
+    s.init_freestream()
+    s.batch_run(1e-300, 5, check_every=5)  # warm-up and graph capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.batch_run(1e-300, B["iters"], check_every=B["iters"])
+    t_batch = time.perf_counter() - t0
+    s.close()
+    t_solo = 0.0
+    for cl, c in zip(clouds, conds):
+        so = ql.Solver(cl, mach=c["mach"], alpha_deg=c["alpha"], **prm)
+        so.init_freestream()
+        so.step(5, want_history=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        so.step(B["iters"], want_history=False)
+        torch.cuda.synchronize()
+        t_solo += time.perf_counter() - t0
+        so.close()
+    return {"cases": B["n_case"], "points_total": total,
+            "points_min_max": [min(cl.n for cl in clouds), max(cl.n for cl in clouds)],
+            "iterations": B["iters"],
+            "batched_mpt_it_s": total * B["iters"] / t_batch / 1e6,
+            "sequential_mpt_it_s": total * B["iters"] / t_solo / 1e6,
+            "speedup": t_solo / t_batch}
 
 
 def _prims(U, gamma=1.4):
@@ -222,6 +271,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-warm-study", action="store_true")
+    ap.add_argument("--no-batch-study", action="store_true")
     ap.add_argument("--precision", choices=("both", "fp64", "mixed"), default="both")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference kernel for "
@@ -331,6 +381,12 @@ def main():
                         "ms_per_step": runs[1]["elapsed"] * 1e3 / args.steps,
                         "over_fp64": runs[1]["value"] / runs[0]["value"],
                         "dtype": "f32 flux body, f64 sums and update"}
+    if not args.no_batch_study:
+        log("batched-cases study")
+        try:
+            out["batched"] = batch_study()
+        except Exception as e:  # reported, never hides the throughput line
+            out["batched"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_warm_study:
         log("warm-start study")
         try:

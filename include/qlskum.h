@@ -80,10 +80,23 @@ typedef struct {
                          way); 0 = the library's default, at most 163840      */
     int32_t grad_lds; /* tuning: the same for the q-derivative sweeps (records
                          of 48 and 80 bytes); 0 = default, at most 163840     */
+    int32_t order;    /* 2: second order, the split fluxes of the modified q
+                         of eq. (28) (sec. 2.1); 1: first-order LSKUM, the
+                         split fluxes of q itself (sec. 2; no q-derivatives
+                         are computed in ql_step, the limiter is unused).
+                         Switching between ql_step calls is allowed: a
+                         first-order start-up followed by second order     */
+    int32_t flux_split;/* 0: one fused flux sweep; 1 (FP64, second order): the
+                         s-direction split fluxes in one launch and the
+                         n-direction ones with the update in a second (fewer
+                         registers per launch, the reconstruction done twice;
+                         the residual's summation grouping changes in the
+                         last bits)                                          */
 } ql_params;
 
 /* Fill *p with the defaults: gamma 1.4, M 0.63, alpha 2, CFL 0.2, 3 inner
- * iterations, limiter off (K = 5), FP64, Hilbert reorder. */
+ * iterations, limiter off (K = 5), FP64, Hilbert reorder, default LDS
+ * budgets (0), second order, fused flux sweep. */
 void ql_default_params(ql_params *p);
 
 /* Create a solver on HIP device `device`.  `hip_stream` is a hipStream_t

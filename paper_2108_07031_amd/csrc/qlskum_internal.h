@@ -51,6 +51,7 @@ struct DevCloud {
 struct FlowParams {
     double gamma, gm1inv, cfl, venkat_k;
     int n_inner, limiter;
+    int order;  // 2: modified q of eq. (28); 1: first order (q~ = q)
     // m = 2/(gamma-1) when it is a small integer (5 for gamma = 1.4), so that
     // beta^(-1/(gamma-1)) = (1/sqrt(beta))^m needs no logarithm; 0 otherwise
     int sqrt_pow;
@@ -90,11 +91,12 @@ hipError_t launch_gradk(hipStream_t st, const DevCloud &c, int lds_budget, const
 // stage 0: evaluate only (writes Rout); stages 1..4: residual + SSP-RK stage.
 // q32next (nullable) receives the FP32 shadow of the new q.  lds_budget =
 // bytes of LDS a workgroup may stage its tile image in (tiles with larger
-// images read from memory).
+// images read from memory).  Rpart (nullable, [4][n]): split the work into
+// an s-direction launch and an n-direction + update launch.
 hipError_t launch_flux(hipStream_t st, const DevCloud &c, const FlowParams &fp, int stage,
                        int lds_budget, const double2 *q, const double2 *g, const double2 *qmm,
                        double *U, double *Un, double *dt, double2 *qnext, double *Rout,
-                       float4 *q32next, int *err);
+                       float4 *q32next, int *err, double *Rpart);
 // mixed precision: reconstruction, limiter and split fluxes in FP32 from the
 // shadows q32, g32, qmm32; weights, residual sums and the update in FP64.
 hipError_t launch_flux_mixed(hipStream_t st, const DevCloud &c, const FlowParams &fp, int stage,

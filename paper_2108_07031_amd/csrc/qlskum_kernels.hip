@@ -403,10 +403,6 @@ hipError_t launch_prep(hipStream_t st, const DevCloud &c, const FlowParams &fp, 
 // ---------------------------------------------------------------------------
 namespace {
 
-// entries per lane whose indices a gradient sweep loads before using them
-// (interior points have 24 neighbours: two chunks of 3 per lane)
-constexpr int kChunk = 3;
-
 __device__ __forceinline__ double lane_group_max(double v) {
     v = fmax(v, __shfl_xor(v, 1, 64));
     return fmax(v, __shfl_xor(v, 2, 64));
@@ -460,24 +456,13 @@ __global__ void __launch_bounds__(kBlock) k_grad0(DevCloud cl, int cap,
     if (cl.tile_active && !cl.tile_active[t]) return;
     const TileInfo ti = tile_info(cl, t, cap);
     if (ti.in_lds) {
-        // one whole record per slot and lane, two slots per pass: all loads
-        // of a pass are independent
-        for (int s0 = threadIdx.x; s0 < ti.ns; s0 += 2 * kBlock) {
-            const int s1 = s0 + kBlock;
+        for (int s0 = threadIdx.x; s0 < ti.ns; s0 += kBlock) {
             const int p0 = slot_point(cl, ti, s0);
-            const int p1 = (s1 < ti.ns) ? slot_point(cl, ti, s1) : -1;
-            const int c0 = p0 >= 0 ? p0 : 0, c1 = p1 >= 0 ? p1 : 0;  // in-range reads
-            const double2 a0 = q[2 * c0], a1 = q[2 * c0 + 1], a2 = cl.xy[c0];
-            const double2 b0 = q[2 * c1], b1 = q[2 * c1 + 1], b2 = cl.xy[c1];
             if (p0 >= 0) {
+                const double2 a0 = q[2 * p0], a1 = q[2 * p0 + 1], a2 = cl.xy[p0];
                 lds[kRec * s0] = a0;
                 lds[kRec * s0 + 1] = a1;
                 lds[kRec * s0 + 2] = a2;
-            }
-            if (p1 >= 0) {
-                lds[kRec * s1] = b0;
-                lds[kRec * s1 + 1] = b1;
-                lds[kRec * s1 + 2] = b2;
             }
         }
     }
@@ -499,39 +484,27 @@ __global__ void __launch_bounds__(kBlock) k_grad0(DevCloud cl, int cap,
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) mx[r] = mn[r] = qp[r];
-        // entries in chunks of kChunk per lane, their indices loaded first.
-        // Past the list's end an entry refers to p itself: dx = dy = dq = 0
-        // add exactly +0 to the sums and leave the bounds unchanged.
         const int k1 = cl.ptr[p + 1];
-        const int self = ti.in_lds ? j : p;
-        for (int k0 = cl.ptr[p] + sub; k0 < k1; k0 += kChunk * kFluxLanes) {
-            int li[kChunk];
-#pragma unroll
-            for (int u = 0; u < kChunk; ++u) {
-                const int k = k0 + u * kFluxLanes;
-                li[u] = (k < k1) ? (ti.in_lds ? (int)cl.flidx[k] : cl.idx[k]) : self;
+        for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
+            double qi[4];
+            double2 Q;
+            if (ti.in_lds) {
+                const double2 *r = lds + kRec * (int)cl.flidx[k];
+                qi[0] = r[0].x; qi[1] = r[0].y; qi[2] = r[1].x; qi[3] = r[1].y;
+                Q = r[2];
+            } else {
+                const int i = cl.idx[k];
+                load4(q, i, qi);
+                Q = cl.xy[i];
             }
+            const double dx = Q.x - P.x, dy = Q.y - P.y;
 #pragma unroll
-            for (int u = 0; u < kChunk; ++u) {
-                double qi[4];
-                double2 Q;
-                if (ti.in_lds) {
-                    const double2 *r = lds + kRec * li[u];
-                    qi[0] = r[0].x; qi[1] = r[0].y; qi[2] = r[1].x; qi[3] = r[1].y;
-                    Q = r[2];
-                } else {
-                    load4(q, li[u], qi);
-                    Q = cl.xy[li[u]];
-                }
-                const double dx = Q.x - P.x, dy = Q.y - P.y;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const double dq = qi[r] - qp[r];
-                    sx[r] = fma(dx, dq, sx[r]);
-                    sy[r] = fma(dy, dq, sy[r]);
-                    mx[r] = fmax(mx[r], qi[r]);
-                    mn[r] = fmin(mn[r], qi[r]);
-                }
+            for (int r = 0; r < 4; ++r) {
+                const double dq = qi[r] - qp[r];
+                sx[r] = fma(dx, dq, sx[r]);
+                sy[r] = fma(dy, dq, sy[r]);
+                mx[r] = fmax(mx[r], qi[r]);
+                mn[r] = fmin(mn[r], qi[r]);
             }
         }
     }
@@ -560,6 +533,10 @@ __global__ void __launch_bounds__(kBlock) k_grad0(DevCloud cl, int cap,
     }
 }
 
+// entry slots an inner-iteration workgroup stages in LDS (tiles with more
+// entries read them from memory)
+constexpr int kCapE = 2048;
+
 // one inner iteration (eq. (29)).  The least squares is linear in its data:
 //   g^k = LS(dq_i) - 1/2 LS(d.(g^{k-1}_i - g^{k-1}_p)) = g0 - 1/2 LS(...)
 // so only the previous iterate is gathered (Jacobi: read gprev, write gnext).
@@ -571,9 +548,27 @@ __global__ void __launch_bounds__(kBlock) k_gradk(DevCloud cl, int cap,
                                                   float4 *__restrict__ g32) {
     constexpr int kRec = 5;
     extern __shared__ double2 lds[];
+    uint16_t *eidx = reinterpret_cast<uint16_t *>(lds + (size_t)kRec * cap);
     const int t = logical_block();
     if (cl.tile_active && !cl.tile_active[t]) return;
     const TileInfo ti = tile_info(cl, t, cap);
+    const int j = threadIdx.x / kFluxLanes, sub = threadIdx.x % kFluxLanes;
+    const int p = ti.base + j;
+    const bool own = j < ti.nown;
+    int kb = 0, k1 = 0;
+    double L0 = 0.0, L1 = 0.0, L2 = 0.0;
+    double2 z = make_double2(0.0, 0.0), gq = make_double2(0.0, 0.0);
+    if (own) {
+        kb = cl.ptr[p];
+        k1 = cl.ptr[p + 1];
+        L0 = cl.lsi[3 * p];
+        L1 = cl.lsi[3 * p + 1];
+        L2 = cl.lsi[3 * p + 2];
+        z = g0[4 * p + sub];
+        gq = gprev[4 * p + sub];
+    }
+    const int e0 = cl.ptr[ti.base], ne = cl.ptr[ti.base + ti.nown] - e0;
+    const bool e_lds = ti.in_lds && ne <= kCapE;
     if (ti.in_lds) {
         for (int s0 = threadIdx.x; s0 < ti.ns; s0 += 2 * kBlock) {
             const int s1 = s0 + kBlock;
@@ -593,12 +588,12 @@ __global__ void __launch_bounds__(kBlock) k_gradk(DevCloud cl, int cap,
                 d[0] = b0; d[1] = b1; d[2] = b2; d[3] = b3; d[4] = b4;
             }
         }
+        if (e_lds)
+            for (int e = threadIdx.x; e < ne; e += kBlock) eidx[e] = cl.flidx[e0 + e];
     }
     __syncthreads();
-    const int j = threadIdx.x / kFluxLanes, sub = threadIdx.x % kFluxLanes;
-    const int p = ti.base + j;
     double sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
-    if (j < ti.nown) {
+    if (own) {
         double gp[8];
         double2 P;
         if (ti.in_lds) {
@@ -613,39 +608,30 @@ __global__ void __launch_bounds__(kBlock) k_gradk(DevCloud cl, int cap,
             load8(gprev, p, gp);
             P = cl.xy[p];
         }
-        // chunks as in k_grad0 (an entry past the end refers to p: +0)
-        const int k1 = cl.ptr[p + 1];
-        const int self = ti.in_lds ? j : p;
-        for (int k0 = cl.ptr[p] + sub; k0 < k1; k0 += kChunk * kFluxLanes) {
-            int li[kChunk];
+#pragma unroll 1
+        for (int k = kb + sub; k < k1; k += kFluxLanes) {
+            double gi[8];
+            double2 Q;
+            if (ti.in_lds) {
+                const int li = e_lds ? (int)eidx[k - e0] : (int)cl.flidx[k];
+                const double2 *r = lds + kRec * li;
 #pragma unroll
-            for (int u = 0; u < kChunk; ++u) {
-                const int k = k0 + u * kFluxLanes;
-                li[u] = (k < k1) ? (ti.in_lds ? (int)cl.flidx[k] : cl.idx[k]) : self;
+                for (int m = 0; m < 4; ++m) {
+                    gi[2 * m] = r[m].x;
+                    gi[2 * m + 1] = r[m].y;
+                }
+                Q = r[4];
+            } else {
+                const int i = cl.idx[k];
+                load8(gprev, i, gi);
+                Q = cl.xy[i];
             }
+            const double dx = Q.x - P.x, dy = Q.y - P.y;
 #pragma unroll
-            for (int u = 0; u < kChunk; ++u) {
-                double gi[8];
-                double2 Q;
-                if (ti.in_lds) {
-                    const double2 *r = lds + kRec * li[u];
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        gi[2 * m] = r[m].x;
-                        gi[2 * m + 1] = r[m].y;
-                    }
-                    Q = r[4];
-                } else {
-                    load8(gprev, li[u], gi);
-                    Q = cl.xy[li[u]];
-                }
-                const double dx = Q.x - P.x, dy = Q.y - P.y;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const double f = fma(dx, gi[r] - gp[r], dy * (gi[4 + r] - gp[4 + r]));
-                    sx[r] = fma(dx, f, sx[r]);
-                    sy[r] = fma(dy, f, sy[r]);
-                }
+            for (int r = 0; r < 4; ++r) {
+                const double f = fma(dx, gi[r], dy * gi[4 + r]);
+                sx[r] = fma(dx, f, sx[r]);
+                sy[r] = fma(dy, f, sy[r]);
             }
         }
     }
@@ -654,16 +640,14 @@ __global__ void __launch_bounds__(kBlock) k_gradk(DevCloud cl, int cap,
         sx[r] = lane_group_sum(sx[r]);
         sy[r] = lane_group_sum(sy[r]);
     }
-    if (j >= ti.nown) return;
-    const double L0 = cl.lsi[3 * p], L1 = cl.lsi[3 * p + 1], L2 = cl.lsi[3 * p + 2];
+    if (!own) return;
     // lane sub produces components 2 sub, 2 sub + 1 of (q_x[0..3], q_y[0..3])
-    const double2 z = g0[4 * p + sub];
     double v[2];
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
         const int c = 2 * sub + m, r = c & 3;
         const double ls = (c < 4) ? fma(L0, sx[r], -(L1 * sy[r])) : fma(L2, sy[r], -(L1 * sx[r]));
-        v[m] = fma(-0.5, ls, m == 0 ? z.x : z.y);
+        v[m] = fma(-0.5, ls - (m == 0 ? gq.x : gq.y), m == 0 ? z.x : z.y);
     }
     gnext[4 * p + sub] = make_double2(v[0], v[1]);
     if (g32) {
@@ -694,7 +678,8 @@ hipError_t launch_gradk(hipStream_t st, const DevCloud &c, int lds_budget, const
                         const double2 *gprev, double2 *gnext, float4 *g32) {
     const int rec = 5 * (int)sizeof(double2);
     const int cap = lds_cap(c, lds_budget, rec);
-    hipLaunchKernelGGL(k_gradk, dim3(num_flux_tiles(c.n)), dim3(kBlock), (size_t)cap * rec, st, c,
+    const size_t shmem = cap > 0 ? (size_t)cap * rec + 2 * kCapE : 0;
+    hipLaunchKernelGGL(k_gradk, dim3(num_flux_tiles(c.n)), dim3(kBlock), shmem, st, c,
                        cap, g0, gprev, gnext, g32);
     return hipGetLastError();
 }
@@ -790,8 +775,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Written with explicit fma and no implicit contraction: a point's residual
 // depends only on its data and on the order of its entries, never on the code
 // path that gathered them.  Returns false when a modified state has no
-// Maxwellian.
-template <bool LIMITER, int POW>
+// Maxwellian.  FIRST: first-order scheme, the split fluxes of q itself.
+// DIRS: the split directions evaluated (1 s, 2 n, 3 both).
+template <bool LIMITER, int POW, bool FIRST, int DIRS = 3>
 __device__ __forceinline__ bool flux_entry(uint8_t f, double dx, double dy, double2 N,
                                            const double qi[4], const double gi[8],
                                            const double bi[8], const double qp[4],
@@ -803,7 +789,13 @@ __device__ __forceinline__ bool flux_entry(uint8_t f, double dx, double dy, doub
     const double ds = fma(dx, tx, dy * ty);
     const double dn = fma(dx, N.x, dy * N.y);
     double qti[4], qt0[4];
-    if (LIMITER) {
+    if (FIRST) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            qti[r] = qi[r];
+            qt0[r] = qp[r];
+        }
+    } else if (LIMITER) {
         const double e = fp.venkat_k * sqrt(fma(dx, dx, dy * dy));
         const double eps2 = (e * e) * e;
 #pragma unroll
@@ -823,7 +815,7 @@ __device__ __forceinline__ bool flux_entry(uint8_t f, double dx, double dy, doub
     Prim si, s0;
     bool ok = q_to_prim<POW>(qti, fp, si);
     ok &= q_to_prim<POW>(qt0, fp, s0);
-    if (f & (kSPlus | kSMinus)) {
+    if ((DIRS & 1) && (f & (kSPlus | kSMinus))) {
         const bool plus = (f & kSPlus) != 0;
         const double sg = plus ? 1.0 : -1.0;
         const double wt = fma(ds, plus ? w[0] : w[2], -(dn * (plus ? w[1] : w[3])));
@@ -833,7 +825,7 @@ __device__ __forceinline__ bool flux_entry(uint8_t f, double dx, double dy, doub
 #pragma unroll
         for (int r = 0; r < 4; ++r) R[r] = fma(wt, Gi[r] - G0[r], R[r]);
     }
-    if (f & (kNPlus | kNMinus)) {
+    if ((DIRS & 2) && (f & (kNPlus | kNMinus))) {
         const bool plus = (f & kNPlus) != 0;
         const double sg = plus ? 1.0 : -1.0;
         const double wt = fma(dn, plus ? w[4] : w[6], -(ds * (plus ? w[5] : w[7])));
@@ -906,8 +898,9 @@ __device__ __forceinline__ void rk_update(const DevCloud &cl, const FlowParams &
 // ---------------------------------------------------------------------------
 int num_flux_tiles(int n) { return (n + kFluxTile - 1) / kFluxTile; }
 
-template <bool LIMITER, int POW>
+template <bool LIMITER, int POW, bool FIRST, int DIRS>
 __global__ void __launch_bounds__(kBlock) k_flux(DevCloud cl, FlowParams fp, int stage, int cap,
+                                                 const double *__restrict__ Rin,
                                                  const double2 *__restrict__ q,
                                                  const double2 *__restrict__ g,
                                                  const double2 *__restrict__ qmm,
@@ -917,7 +910,8 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevCloud cl, FlowParams fp, int
                                                  double *__restrict__ Rout,
                                                  float4 *__restrict__ q32next, int *err) {
     // slot record (double2): q 0..1, g 2..5, bounds 6..9, position last
-    constexpr int kRec = LIMITER ? 11 : 7;
+    // (first order: q and position only)
+    constexpr int kRec = FIRST ? 3 : (LIMITER ? 11 : 7);
     extern __shared__ double2 lds[];
     const int n = cl.n;
     const int t = logical_block();
@@ -939,7 +933,7 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevCloud cl, FlowParams fp, int
             if (s >= nown && s < kFluxTile) continue;
             lds[kRec * s + (e & 1)] = q[2 * slot_point(s) + (e & 1)];
         }
-        for (int e = threadIdx.x; e < 4 * ns; e += kBlock) {
+        for (int e = threadIdx.x; !FIRST && e < 4 * ns; e += kBlock) {
             const int s = e >> 2;
             if (s >= nown && s < kFluxTile) continue;
             const int pt = slot_point(s);
@@ -971,7 +965,7 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevCloud cl, FlowParams fp, int
             const double2 *r = lds + kRec * j;
             qp[0] = r[0].x; qp[1] = r[0].y; qp[2] = r[1].x; qp[3] = r[1].y;
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
+            for (int m = 0; m < 4 && !FIRST; ++m) {
                 gp[2 * m] = r[2 + m].x;
                 gp[2 * m + 1] = r[2 + m].y;
                 if (LIMITER) {
@@ -982,15 +976,19 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevCloud cl, FlowParams fp, int
             P = r[kRec - 1];
         } else {
             load4(q, p, qp);
-            load8(g, p, gp);
+            if (!FIRST) load8(g, p, gp);
             if (LIMITER) load8(qmm, p, bp);
             P = cl.xy[p];
         }
 #pragma unroll
         for (int m = 0; m < 8; ++m) w[m] = cl.lsw[8 * p + m];
-        const uint8_t fmask = (kd == kWall) ? uint8_t(~kNPlus) : uint8_t(0xff);
+        constexpr uint8_t kDirMask = (DIRS == 1)   ? uint8_t(kSPlus | kSMinus)
+                                     : (DIRS == 2) ? uint8_t(kNPlus | kNMinus)
+                                                   : uint8_t(0xff);
+        const uint8_t fmask = ((kd == kWall) ? uint8_t(~kNPlus) : uint8_t(0xff)) & kDirMask;
         const int k1 = cl.ptr[p + 1];
         bool ok = true;
+#pragma unroll 2
         for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
             const uint8_t f = cl.flag[k] & fmask;
             if (f == 0) continue;
@@ -1000,7 +998,7 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevCloud cl, FlowParams fp, int
                 const double2 *r = lds + kRec * (int)cl.flidx[k];
                 qi[0] = r[0].x; qi[1] = r[0].y; qi[2] = r[1].x; qi[3] = r[1].y;
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
+                for (int m = 0; m < 4 && !FIRST; ++m) {
                     gi[2 * m] = r[2 + m].x;
                     gi[2 * m + 1] = r[2 + m].y;
                     if (LIMITER) {
@@ -1012,18 +1010,22 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevCloud cl, FlowParams fp, int
             } else {
                 const int i = cl.idx[k];
                 load4(q, i, qi);
-                load8(g, i, gi);
+                if (!FIRST) load8(g, i, gi);
                 if (LIMITER) load8(qmm, i, bi);
                 Q = cl.xy[i];
             }
-            ok &= flux_entry<LIMITER, POW>(f, Q.x - P.x, Q.y - P.y, N, qi, gi, bi, qp, gp, bp, w,
-                                           fp, R);
+            ok &= flux_entry<LIMITER, POW, FIRST, DIRS>(f, Q.x - P.x, Q.y - P.y, N, qi, gi, bi, qp,
+                                                        gp, bp, w, fp, R);
         }
         if (!ok) report(err, p, kErrPositivity);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) R[r] = lane_group_sum(R[r]);
     if (j >= nown || sub != 0) return;
+    if (Rin && live) {  // the other directions' part (split launches)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) R[r] += Rin[(size_t)r * n + p];
+    }
     if (!live) {
         if (stage > 0) {
             double qv[4];
@@ -1047,21 +1049,34 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevCloud cl, FlowParams fp, int
 hipError_t launch_flux(hipStream_t st, const DevCloud &c, const FlowParams &fp, int stage,
                        int lds_budget, const double2 *q, const double2 *g, const double2 *qmm,
                        double *U, double *Un, double *dt, double2 *qnext, double *Rout,
-                       float4 *q32next, int *err) {
-    const int rec = (fp.limiter ? 11 : 7) * (int)sizeof(double2);
+                       float4 *q32next, int *err, double *Rpart) {
+    const bool first = fp.order == 1;
+    const int rec = (first ? 3 : fp.limiter ? 11 : 7) * (int)sizeof(double2);
     const int cap = lds_cap(c, lds_budget, rec);
     const size_t shmem = (size_t)cap * rec;
     const dim3 grid(num_flux_tiles(c.n)), block(kBlock);
-#define QL_FLUX_LAUNCH(LIM, POW)                                                          \
-    hipLaunchKernelGGL((k_flux<LIM, POW>), grid, block, shmem, st, c, fp, stage, cap, q, g, \
-                       qmm, U, Un, dt, qnext, Rout, q32next, err)
-    if (fp.sqrt_pow == 5) {  // gamma = 1.4
-        if (fp.limiter) QL_FLUX_LAUNCH(true, 5);
-        else QL_FLUX_LAUNCH(false, 5);
-    } else {
-        if (fp.limiter) QL_FLUX_LAUNCH(true, 0);
-        else QL_FLUX_LAUNCH(false, 0);
+#define QL_FLUX_LAUNCH(LIM, POW, FIRST, DIRS, STAGE, RIN, ROUT)                            \
+    hipLaunchKernelGGL((k_flux<LIM, POW, FIRST, DIRS>), grid, block, shmem, st, c, fp, STAGE, \
+                       cap, RIN, q, g, qmm, U, Un, dt, qnext, ROUT, q32next, err)
+    // Rpart != null: the s directions in one launch (into Rpart), the n
+    // directions and the update in a second one (fewer registers each)
+#define QL_FLUX_DISPATCH(LIM, POW)                                                       \
+    if (Rpart) {                                                                         \
+        QL_FLUX_LAUNCH(LIM, POW, false, 1, 0, (const double *)nullptr, Rpart);         \
+        QL_FLUX_LAUNCH(LIM, POW, false, 2, stage, (const double *)Rpart, Rout);        \
+    } else {                                                                             \
+        QL_FLUX_LAUNCH(LIM, POW, false, 3, stage, (const double *)nullptr, Rout);      \
     }
+    if (fp.sqrt_pow == 5) {  // gamma = 1.4
+        if (first) QL_FLUX_LAUNCH(false, 5, true, 3, stage, (const double *)nullptr, Rout);
+        else if (fp.limiter) { QL_FLUX_DISPATCH(true, 5) }
+        else { QL_FLUX_DISPATCH(false, 5) }
+    } else {
+        if (first) QL_FLUX_LAUNCH(false, 0, true, 3, stage, (const double *)nullptr, Rout);
+        else if (fp.limiter) { QL_FLUX_DISPATCH(true, 0) }
+        else { QL_FLUX_DISPATCH(false, 0) }
+    }
+#undef QL_FLUX_DISPATCH
 #undef QL_FLUX_LAUNCH
     return hipGetLastError();
 }
@@ -1137,7 +1152,7 @@ __device__ __forceinline__ void unpack(const float4 a, float *v) {
 }
 
 // FP32 counterpart of flux_entry; the weights and sums stay FP64.
-template <bool LIMITER, int POW>
+template <bool LIMITER, int POW, bool FIRST>
 __device__ __forceinline__ bool flux_entry_f(uint8_t f, double dx, double dy, double2 N,
                                              const float qi[4], const float gi[8],
                                              const float bi[8], const float qp[4],
@@ -1150,7 +1165,13 @@ __device__ __forceinline__ bool flux_entry_f(uint8_t f, double dx, double dy, do
     const double dn = fma(dx, N.x, dy * N.y);
     const float dxf = (float)dx, dyf = (float)dy;
     float qti[4], qt0[4];
-    if (LIMITER) {
+    if (FIRST) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            qti[r] = qi[r];
+            qt0[r] = qp[r];
+        }
+    } else if (LIMITER) {
         const float e = vk * sqrtf(fmaf(dxf, dxf, dyf * dyf));
         const float eps2 = (e * e) * e;
 #pragma unroll
@@ -1195,15 +1216,16 @@ __device__ __forceinline__ bool flux_entry_f(uint8_t f, double dx, double dy, do
 
 }  // namespace
 
-template <bool LIMITER, int POW>
+template <bool LIMITER, int POW, bool FIRST>
 __global__ void __launch_bounds__(kBlock) k_flux_mixed(
     DevCloud cl, FlowParams fp, int stage, int cap, const double2 *__restrict__ q,
     const float4 *__restrict__ q32, const float4 *__restrict__ g32,
     const float4 *__restrict__ qmm32, double *__restrict__ U, double *__restrict__ Un,
     double *__restrict__ dt, double2 *__restrict__ qnext, float4 *__restrict__ q32next,
     double *__restrict__ Rout, int *err) {
-    // slot record (float4): q 0, g 1..2, bounds 3..4; positions after cap records
-    constexpr int kRec = LIMITER ? 5 : 3;
+    // slot record (float4): q 0, g 1..2, bounds 3..4 (first order: q only);
+    // positions after cap records
+    constexpr int kRec = FIRST ? 1 : (LIMITER ? 5 : 3);
     extern __shared__ float4 ldsf[];
     double2 *lxy = reinterpret_cast<double2 *>(ldsf + (size_t)kRec * cap);
     const int n = cl.n;
@@ -1221,7 +1243,7 @@ __global__ void __launch_bounds__(kBlock) k_flux_mixed(
         auto slot_point = [&](int s) {
             return s < kFluxTile ? base + s : cl.fhalo_idx[h0 + s - kFluxTile];
         };
-        for (int e = threadIdx.x; e < 2 * ns; e += kBlock) {
+        for (int e = threadIdx.x; !FIRST && e < 2 * ns; e += kBlock) {
             const int s = e >> 1;
             if (s >= nown && s < kFluxTile) continue;
             const int pt = slot_point(s);
@@ -1257,8 +1279,10 @@ __global__ void __launch_bounds__(kBlock) k_flux_mixed(
         if (in_lds) {
             const float4 *r = ldsf + kRec * j;
             unpack(r[0], qp);
-            unpack(r[1], gp);
-            unpack(r[2], gp + 4);
+            if (!FIRST) {
+                unpack(r[1], gp);
+                unpack(r[2], gp + 4);
+            }
             if (LIMITER) {
                 unpack(r[3], bp);
                 unpack(r[4], bp + 4);
@@ -1266,8 +1290,10 @@ __global__ void __launch_bounds__(kBlock) k_flux_mixed(
             P = lxy[j];
         } else {
             unpack(q32[p], qp);
-            unpack(g32[2 * p], gp);
-            unpack(g32[2 * p + 1], gp + 4);
+            if (!FIRST) {
+                unpack(g32[2 * p], gp);
+                unpack(g32[2 * p + 1], gp + 4);
+            }
             if (LIMITER) {
                 unpack(qmm32[2 * p], bp);
                 unpack(qmm32[2 * p + 1], bp + 4);
@@ -1279,6 +1305,7 @@ __global__ void __launch_bounds__(kBlock) k_flux_mixed(
         const uint8_t fmask = (kd == kWall) ? uint8_t(~kNPlus) : uint8_t(0xff);
         const int k1 = cl.ptr[p + 1];
         bool ok = true;
+#pragma unroll 2
         for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
             const uint8_t f = cl.flag[k] & fmask;
             if (f == 0) continue;
@@ -1288,8 +1315,10 @@ __global__ void __launch_bounds__(kBlock) k_flux_mixed(
                 const int s = cl.flidx[k];
                 const float4 *r = ldsf + kRec * s;
                 unpack(r[0], qi);
-                unpack(r[1], gi);
-                unpack(r[2], gi + 4);
+                if (!FIRST) {
+                    unpack(r[1], gi);
+                    unpack(r[2], gi + 4);
+                }
                 if (LIMITER) {
                     unpack(r[3], bi);
                     unpack(r[4], bi + 4);
@@ -1298,15 +1327,17 @@ __global__ void __launch_bounds__(kBlock) k_flux_mixed(
             } else {
                 const int i = cl.idx[k];
                 unpack(q32[i], qi);
-                unpack(g32[2 * i], gi);
-                unpack(g32[2 * i + 1], gi + 4);
+                if (!FIRST) {
+                    unpack(g32[2 * i], gi);
+                    unpack(g32[2 * i + 1], gi + 4);
+                }
                 if (LIMITER) {
                     unpack(qmm32[2 * i], bi);
                     unpack(qmm32[2 * i + 1], bi + 4);
                 }
                 Q = cl.xy[i];
             }
-            ok &= flux_entry_f<LIMITER, POW>(f, Q.x - P.x, Q.y - P.y, N, qi, gi, bi, qp, gp, bp,
+            ok &= flux_entry_f<LIMITER, POW, FIRST>(f, Q.x - P.x, Q.y - P.y, N, qi, gi, bi, qp, gp, bp,
                                              w, gm1inv, vk, R);
         }
         if (!ok) report(err, p, kErrPositivity);
@@ -1339,19 +1370,22 @@ hipError_t launch_flux_mixed(hipStream_t st, const DevCloud &c, const FlowParams
                              const float4 *g32, const float4 *qmm32, double *U, double *Un,
                              double *dt, double2 *qnext, float4 *q32next, double *Rout,
                              int *err) {
-    const int rec = ((fp.limiter ? 5 : 3) + 1) * (int)sizeof(float4);
+    const bool first = fp.order == 1;
+    const int rec = ((first ? 1 : fp.limiter ? 5 : 3) + 1) * (int)sizeof(float4);
     const int cap = lds_cap(c, lds_budget, rec);
     const size_t shmem = (size_t)cap * rec;
     const dim3 grid(num_flux_tiles(c.n)), block(kBlock);
-#define QL_FLUXM_LAUNCH(LIM, POW)                                                     \
-    hipLaunchKernelGGL((k_flux_mixed<LIM, POW>), grid, block, shmem, st, c, fp, stage, \
+#define QL_FLUXM_LAUNCH(LIM, POW, FIRST)                                                     \
+    hipLaunchKernelGGL((k_flux_mixed<LIM, POW, FIRST>), grid, block, shmem, st, c, fp, stage, \
                        cap, q, q32, g32, qmm32, U, Un, dt, qnext, q32next, Rout, err)
     if (fp.sqrt_pow == 5) {
-        if (fp.limiter) QL_FLUXM_LAUNCH(true, 5);
-        else QL_FLUXM_LAUNCH(false, 5);
+        if (first) QL_FLUXM_LAUNCH(false, 5, true);
+        else if (fp.limiter) QL_FLUXM_LAUNCH(true, 5, false);
+        else QL_FLUXM_LAUNCH(false, 5, false);
     } else {
-        if (fp.limiter) QL_FLUXM_LAUNCH(true, 0);
-        else QL_FLUXM_LAUNCH(false, 0);
+        if (first) QL_FLUXM_LAUNCH(false, 0, true);
+        else if (fp.limiter) QL_FLUXM_LAUNCH(true, 0, false);
+        else QL_FLUXM_LAUNCH(false, 0, false);
     }
 #undef QL_FLUXM_LAUNCH
     return hipGetLastError();

@@ -77,6 +77,7 @@ struct ql_solver {
     double2 *q[2] = {nullptr, nullptr}, *g[3] = {nullptr, nullptr, nullptr}, *qmm = nullptr;
     float4 *q32[2] = {nullptr, nullptr}, *g32 = nullptr, *qmm32 = nullptr;  // FP32 shadows
     double *lsi = nullptr;
+    double *Rpart = nullptr;  // [4][n], the s-direction part of a split flux sweep
     int *fhalo_ptr = nullptr, *fhalo_idx = nullptr;  // tiles of kFluxTile points
     uint16_t *flidx = nullptr;
     int fmax_slots = 0;
@@ -148,7 +149,7 @@ void free_cloud(ql_solver *s) {
     dfree(s->dperm); dfree(s->wall); dfree(s->lsw); dfree(s->dmin); dfree(s->U); dfree(s->Un);
     dfree(s->dt); dfree(s->R); dfree(s->tmp); dfree(s->q[0]); dfree(s->q[1]); dfree(s->g[0]);
     dfree(s->g[1]); dfree(s->g[2]); dfree(s->qmm); dfree(s->reshist);
-    dfree(s->fscratch); dfree(s->fout); dfree(s->errw); dfree(s->lsi);
+    dfree(s->fscratch); dfree(s->fout); dfree(s->errw); dfree(s->lsi); dfree(s->Rpart);
     dfree(s->fhalo_ptr); dfree(s->fhalo_idx); dfree(s->flidx);
     dfree(s->q32[0]); dfree(s->q32[1]); dfree(s->g32); dfree(s->qmm32);
     dfree(s->case_of); dfree(s->chunk_beg); dfree(s->chunk_ptr); dfree(s->ctr);
@@ -279,6 +280,7 @@ FlowParams flow_params(const ql_solver *s) {
     f.venkat_k = s->prm.venkat_k;
     f.n_inner = s->prm.n_inner;
     f.limiter = s->prm.limiter;
+    f.order = s->prm.order;
     const double m = 2.0 / (s->prm.gamma - 1.0);
     const double mr = std::nearbyint(m);
     f.sqrt_pow = (std::fabs(m - mr) <= 1e-12 * m && mr >= 1.0 && mr <= 16.0) ? (int)mr : 0;
@@ -301,6 +303,9 @@ int check_params(ql_solver *s, const ql_params *p) {
         return fail(s, QL_EINVAL, "flux_lds must lie in [0, 163840] bytes");
     if (p->grad_lds < 0 || p->grad_lds > 160 * 1024)
         return fail(s, QL_EINVAL, "grad_lds must lie in [0, 163840] bytes");
+    if (p->order != 1 && p->order != 2) return fail(s, QL_EINVAL, "order must be 1 or 2");
+    if (p->flux_split != 0 && p->flux_split != 1)
+        return fail(s, QL_EINVAL, "flux_split must be 0 or 1");
     return QL_OK;
 }
 
@@ -374,11 +379,13 @@ struct Timer {
 };
 
 // LDS bytes a q-derivative workgroup stages its tile image in (records of
-// 48 and 80 bytes).  Sized so that the workgroups the kernels' register use
-// allows per CU (4 of 256 lanes) stay resident in 160 KB of LDS; the rare
-// tiles with larger images read from memory.
+// 48 and 80 bytes; the inner iteration also stages 4 KB of entry slots).
+// Sized so that the 6 workgroups per CU that the kernels' registers allow
+// stay resident in 160 KB of LDS (measured on the 2.5M cloud: 22 KB runs
+// the inner iteration 12% faster than 36 KB, although a few more tiles then
+// read from memory).
 constexpr int kGrad0Lds = 32 * 1024;
-constexpr int kGradkLds = 36 * 1024;
+constexpr int kGradkLds = 22 * 1024;
 
 // One stage's q-derivatives: first pass + n_inner Jacobi iterations; leaves
 // the final iterate in g[gfin].
@@ -444,7 +451,8 @@ int launch_stage(ql_solver *s, const DevCloud &c, const FlowParams &fp, int stag
                                     s->errw));
     else
         HIPCHK(s, launch_flux(s->stream, c, fp, stage, lds, s->q[a], s->g[s->gfin], s->qmm, s->U,
-                              s->Un, s->dt, s->q[b], Rout, s->q32[b], s->errw));
+                              s->Un, s->dt, s->q[b], Rout, s->q32[b], s->errw,
+                              (s->prm.flux_split && fp.order == 2) ? s->Rpart : nullptr));
     return QL_OK;
 }
 
@@ -452,8 +460,9 @@ int launch_stage(ql_solver *s, const DevCloud &c, const FlowParams &fp, int stag
 // stage 1 into history row *ctr.
 int enqueue_iteration(ql_solver *s, const DevCloud &c, const FlowParams &fp, int hist_cap) {
     for (int rk = 1; rk <= 4; ++rk) {
-        int st = run_gradients(s, c, fp.limiter != 0);
-        if (st) return st;
+        int st = QL_OK;
+        // the first-order scheme needs no q-derivatives
+        if (fp.order == 2 && (st = run_gradients(s, c, fp.limiter != 0))) return st;
         Timer t(s, 2);
         st = launch_stage(s, c, fp, rk, rk == 1 ? s->R : nullptr);
         if (st) return st;
@@ -544,6 +553,8 @@ void ql_default_params(ql_params *p) {
     p->reorder = 1;
     p->flux_lds = 0;
     p->grad_lds = 0;
+    p->order = 2;
+    p->flux_split = 0;
 }
 
 int ql_create(ql_solver **out, int32_t device, void *hip_stream) {
@@ -600,6 +611,7 @@ int ql_set_params(ql_solver *s, const ql_params *p) {
     if (st) return st;
     s->prm = *p;
     drop_graph(s);
+    if (s->has_cloud && p->flux_split && !s->Rpart) HIPCHK(s, dalloc(&s->Rpart, (size_t)4 * s->n));
     return QL_OK;
 }
 
@@ -721,6 +733,7 @@ static int upload_impl(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int
     HIPCHK(s, dalloc(&s->dperm, n)); HIPCHK(s, dalloc(&s->wall, hwall.size()));
     HIPCHK(s, dalloc(&s->lsw, (size_t)8 * n)); HIPCHK(s, dalloc(&s->dmin, n));
     HIPCHK(s, dalloc(&s->lsi, (size_t)3 * n));
+    if (s->prm.flux_split) HIPCHK(s, dalloc(&s->Rpart, (size_t)4 * n));
     HIPCHK(s, dalloc(&s->U, (size_t)4 * n)); HIPCHK(s, dalloc(&s->Un, (size_t)4 * n));
     HIPCHK(s, dalloc(&s->dt, n)); HIPCHK(s, dalloc(&s->R, (size_t)4 * n));
     HIPCHK(s, dalloc(&s->tmp, (size_t)4 * n));
@@ -1238,7 +1251,8 @@ int ql_autotune(ql_solver *s, const char *cache_path, int32_t *chosen) {
         return QL_OK;
     };
     const int flux_c[] = {16, 24 << 10, 32 << 10, 40 << 10, 48 << 10, 52 << 10, 64 << 10, 80 << 10};
-    const int grad_c[] = {16, 16 << 10, 24 << 10, 32 << 10, 40 << 10, 48 << 10};
+    const int grad_c[] = {16, 12 << 10, 16 << 10, 20 << 10, 22 << 10, 24 << 10, 28 << 10,
+                          32 << 10};
     const ql_params saved = s->prm;
     double best_f = 1e30, best_g = 1e30, us = 0.0;
     if ((st = reset_err(s)) || (st = prep_state(s)) || (st = run_gradients(s, c, fp.limiter != 0)))

@@ -40,7 +40,8 @@ class ql_params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("mach", C.c_double), ("alpha_deg", C.c_double),
                 ("cfl", C.c_double), ("n_inner", C.c_int32), ("limiter", C.c_int32),
                 ("venkat_k", C.c_double), ("precision", C.c_int32), ("reorder", C.c_int32),
-                ("flux_lds", C.c_int32), ("grad_lds", C.c_int32)]
+                ("flux_lds", C.c_int32), ("grad_lds", C.c_int32), ("order", C.c_int32),
+                ("flux_split", C.c_int32)]
 
 
 class QLError(RuntimeError):
@@ -478,6 +479,7 @@ class Solver:
 
     def __init__(self, cloud=None, device=0, stream=None, **prm):
         self.h = ql_create(device, stream)
+        self._prm = dict(prm)
         if prm:
             ql_set_params(self.h, params(**prm))
         if cloud is not None:
@@ -502,7 +504,9 @@ class Solver:
         return ql_wall_distance(self.h)
 
     def autotune(self, cache_path=None):
-        return ql_autotune(self.h, cache_path)
+        f, g = ql_autotune(self.h, cache_path)
+        self._prm.update(flux_lds=f, grad_lds=g)
+        return f, g
 
     def warm_start(self, mlp, X, out_scale, rel_floor=0.05):
         n, _ = ql_cloud_size(self.h)
@@ -518,7 +522,10 @@ class Solver:
                         cloud.nbr_ptr, cloud.nbr_idx, nbr_flag)
 
     def set_params(self, **prm):
-        ql_set_params(self.h, params(**prm))
+        """Change the given parameters, keeping the others."""
+        merged = dict(self._prm, **prm)
+        ql_set_params(self.h, params(**merged))
+        self._prm = merged
 
     def init_freestream(self):
         ql_init_freestream(self.h)

@@ -221,3 +221,58 @@ def test_c2_full_size_evaluate(ql):
         err = normwise_rel(gpu[key], ora[key])
         _say(f"  {key}: gpu {err.max():.2e}  floor {floor.max():.2e}")
         assert np.all(err <= 10.0 * floor + 1e-14), (key, err, floor)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_first_order_parity(ql, precision):
+    """First-order mode (order = 1, split fluxes of q itself): one evaluation
+    against the oracle's first-order residual (FP64 5e-12, mixed 2e-3), and
+    in FP64 a first-order start-up of 60 iterations switched to second order
+    for 40 more, against the oracle doing the same (1e-11 per component)."""
+    _say(f"first order precision={precision}")
+    c = cloud("c1")
+    U = smooth_state(c)
+    ora1 = oracle.Oracle(c, oracle.params(order=1))
+    s = ql.Solver(c, order=1, precision=precision)
+    s.set_state(U)
+    R = s.evaluate()["R"]
+    err = normwise_rel(R, ora1.evaluate(U)["R"])
+    _say(f"  R error {err}")
+    assert np.all(err <= (5e-12 if precision == 0 else 2e-3)), err
+    if precision == 0:
+        s.init_freestream()
+        U0 = s.fetch_state()
+        s.step(60)
+        s.set_params(order=2)
+        s.step(40)
+        U1, _ = ora1.run(U0, 60)
+        U2, _ = oracle.Oracle(c, oracle.params(order=2)).run(U1, 40)
+        err = normwise_rel(s.fetch_state(), U2)
+        _say(f"  start-up state error {err}")
+        assert np.all(err <= 1e-11), err
+    s.close()
+
+
+@pytest.mark.parametrize("limiter", [0, 1])
+def test_split_flux_sweep(ql, limiter):
+    """flux_split = 1 (s directions and n directions in two launches) gives
+    the fused sweep's residual up to the summation grouping (1e-13) and the
+    oracle's within the evaluation bound (5e-12); 20 iterations stay within
+    1e-12 of the fused run."""
+    _say(f"split flux sweep limiter={limiter}")
+    c = cloud("jitter")
+    prm = dict(limiter=limiter, mach=0.85 if limiter else 0.63, alpha_deg=1.0 if limiter else 2.0)
+    U = smooth_state(c, mach=prm["mach"], alpha_deg=prm["alpha_deg"])
+    ora = oracle.Oracle(c, oracle.params(**prm)).evaluate(U)
+    out = {}
+    for split in (0, 1):
+        s = ql.Solver(c, flux_split=split, **prm)
+        s.set_state(U)
+        R = s.evaluate()["R"]
+        s.set_state(U)
+        s.step(20)
+        out[split] = (R, s.fetch_state())
+        s.close()
+    assert np.all(normwise_rel(out[1][0], out[0][0]) <= 1e-13)
+    assert np.all(normwise_rel(out[1][0], ora["R"]) <= 5e-12)
+    assert np.all(normwise_rel(out[1][1], out[0][1]) <= 1e-12)
