@@ -90,7 +90,7 @@ def _surface_normals(sx, sy):
 
 def naca_ocloud(ns, nr, tau=0.12, r_outer=15.0, q_stretch=1.08 ** 59,
                 jitter=0.0, seed=2108, stencil="box", box_halfwidth=2,
-                radius_factor=2.5, max_neighbours=25, smooth=1.0 / 40.0):
+                radius_factor=2.5, max_neighbours=25, smooth=1.0 / 40.0, progress=None):
     """O-type cloud of ns x nr points around a NACA 00xx airfoil.
 
     Layer j sits at the blend parameter w_j = (Q^{t_j} - 1)/(Q - 1),
@@ -122,6 +122,9 @@ def naca_ocloud(ns, nr, tau=0.12, r_outer=15.0, q_stretch=1.08 ** 59,
     `jitter` moves interior points by U(-jitter, jitter) times the local
     tangential and radial lattice spacing (splitmix64 stream seeded with
     `seed`: two draws per interior point in user order, tangential first).
+
+    `progress`, if given, is called with a short message after each chunk
+    of work (large clouds take minutes).
     """
     if ns % 2 or ns < 8 or nr < 3:
         raise ValueError("ns must be even and >= 8, nr >= 3")
@@ -201,8 +204,10 @@ def naca_ocloud(ns, nr, tau=0.12, r_outer=15.0, q_stretch=1.08 ** 59,
     NXf, NYf = NX.reshape(-1).copy(), NY.reshape(-1).copy()
     kindf = kind.reshape(-1)
     if stencil == "box":
-        ptr, idx = lattice_box_neighbours(x, y, ns, nr, box_halfwidth, max_neighbours)
-        ptr, idx = enrich_half_planes(x, y, NXf, NYf, kindf, ptr, idx, max_neighbours)
+        ptr, idx = lattice_box_neighbours(x, y, ns, nr, box_halfwidth, max_neighbours,
+                                          progress=progress)
+        ptr, idx = enrich_half_planes(x, y, NXf, NYf, kindf, ptr, idx, max_neighbours,
+                                      progress=progress)
     elif stencil == "radius":
         h_p = np.maximum.reduce([et_next, et_prev, er_next, er_prev])
         ptr, idx = radius_neighbours(x, y, radius_factor * h_p.reshape(-1), max_neighbours,
@@ -215,6 +220,36 @@ def naca_ocloud(ns, nr, tau=0.12, r_outer=15.0, q_stretch=1.08 ** 59,
     return cloud
 
 
+
+
+def naca_ocloud_cached(path, ns, nr, **kw):
+    """naca_ocloud(ns, nr, **kw), kept in an uncompressed .npz at `path`:
+    loaded from there when the file holds a cloud made with the same
+    arguments, else built and written (large clouds take minutes to build
+    and seconds to load).  `progress` is passed through and not stored."""
+    import json
+    import os
+    progress = kw.pop("progress", None)
+    key = json.dumps(dict(ns=ns, nr=nr, **kw), sort_keys=True)
+    if path and os.path.exists(path):
+        with np.load(path, allow_pickle=False) as z:
+            if str(z["key"]) == key:
+                c = Cloud(x=z["x"], y=z["y"], nx=z["nx"], ny=z["ny"], kind=z["kind"],
+                          nbr_ptr=z["nbr_ptr"], nbr_idx=z["nbr_idx"],
+                          meta=json.loads(str(z["meta"])))
+                if progress is not None:
+                    progress(f"cloud loaded from {path}")
+                return c
+    c = naca_ocloud(ns, nr, progress=progress, **kw)
+    if path:
+        tmp = path + ".tmp.npz"
+        np.savez(tmp, key=np.array(key), meta=np.array(json.dumps(c.meta, sort_keys=True)),
+                 x=c.x, y=c.y, nx=c.nx, ny=c.ny, kind=c.kind, nbr_ptr=c.nbr_ptr,
+                 nbr_idx=c.nbr_idx)
+        os.replace(tmp, path)
+        if progress is not None:
+            progress(f"cloud written to {path}")
+    return c
 
 def _departure_directions(wnx, wny, smooth):
     """Wall normals with their angle smoothed (periodic Gaussian of width
@@ -237,31 +272,40 @@ def _departure_directions(wnx, wny, smooth):
     return np.cos(th2), np.sin(th2)
 
 
-def _half_plane_quality(x, y, nx, ny, kind, ptr, idx):
+def _half_plane_quality(x, y, nx, ny, kind, ptr, idx, chunk=1 << 20, progress=None):
     """Per point and half plane (s<0, s>0, n<0, n>0 in the point's frame),
     the count and the normalised determinant det/(sum ds^2 + sum dn^2)^2 of
     the 2x2 moment matrix of the neighbour offsets in that half plane, and
     whether the half plane is needed (interior: all four; wall: all but
-    n<0, which lies in the body; outer: none)."""
+    n<0, which lies in the body; outer: none).  Points are processed in
+    chunks so that the per-entry temporaries stay small."""
     n = x.shape[0]
-    owner = np.repeat(np.arange(n), np.diff(ptr))
-    dx = x[idx] - x[owner]
-    dy = y[idx] - y[owner]
-    ds = dx * ny[owner] - dy * nx[owner]
-    dn = dx * nx[owner] + dy * ny[owner]
-    tie = 1e-24 * (dx * dx + dy * dy)
-    halves = [(ds * ds > tie) & (ds < 0), (ds * ds > tie) & (ds > 0),
-              (dn * dn > tie) & (dn < 0), (dn * dn > tie) & (dn > 0)]
     cnt = np.zeros((4, n))
     qual = np.zeros((4, n))
-    for h, m in enumerate(halves):
-        w = m.astype(np.float64)
-        ss = np.bincount(owner, w * ds * ds, minlength=n)
-        sn = np.bincount(owner, w * ds * dn, minlength=n)
-        nn = np.bincount(owner, w * dn * dn, minlength=n)
-        cnt[h] = np.bincount(owner, w, minlength=n)
-        sc = ss + nn
-        qual[h] = np.where(sc > 0, (ss * nn - sn * sn) / np.where(sc > 0, sc * sc, 1.0), 0.0)
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        m_ = hi - lo
+        loc = np.repeat(np.arange(m_), np.diff(ptr[lo:hi + 1]))
+        owner = loc + lo
+        nb = idx[int(ptr[lo]):int(ptr[hi])]
+        dx = x[nb] - x[owner]
+        dy = y[nb] - y[owner]
+        ds = dx * ny[owner] - dy * nx[owner]
+        dn = dx * nx[owner] + dy * ny[owner]
+        tie = 1e-24 * (dx * dx + dy * dy)
+        halves = [(ds * ds > tie) & (ds < 0), (ds * ds > tie) & (ds > 0),
+                  (dn * dn > tie) & (dn < 0), (dn * dn > tie) & (dn > 0)]
+        for h, m in enumerate(halves):
+            w = m.astype(np.float64)
+            ss = np.bincount(loc, w * ds * ds, minlength=m_)
+            sn = np.bincount(loc, w * ds * dn, minlength=m_)
+            nn = np.bincount(loc, w * dn * dn, minlength=m_)
+            cnt[h, lo:hi] = np.bincount(loc, w, minlength=m_)
+            sc = ss + nn
+            qual[h, lo:hi] = np.where(sc > 0, (ss * nn - sn * sn) / np.where(sc > 0, sc * sc, 1.0),
+                                      0.0)
+        if progress is not None:
+            progress(f"split half planes {hi}/{n}")
     need = np.ones((4, n), dtype=bool)
     need[:, kind == KIND_OUTER] = False
     need[2, kind == KIND_WALL] = False
@@ -269,14 +313,16 @@ def _half_plane_quality(x, y, nx, ny, kind, ptr, idx):
 
 
 def enrich_half_planes(x, y, nx, ny, kind, ptr, idx, cap, min_quality=1e-4, min_count=3,
-                       pool=1024):
+                       pool=1024, progress=None):
     """Add neighbours where a needed split half plane is poorly conditioned
     (fewer than `min_count` points or a normalised determinant below
     `min_quality`, e.g. the on-axis points behind a sharp trailing edge): the
     nearest points of that half plane not yet in the stencil that improve
     it, one at a time, until both bounds hold (at most `cap` neighbours)."""
-    cnt, qual, need = _half_plane_quality(x, y, nx, ny, kind, ptr, idx)
+    cnt, qual, need = _half_plane_quality(x, y, nx, ny, kind, ptr, idx, progress=progress)
     bad = np.flatnonzero(np.any(need & ((cnt < min_count) | (qual <= min_quality)), axis=0))
+    if progress is not None:
+        progress(f"split half planes checked: {bad.size} points to repair")
     if bad.size == 0:
         return ptr, idx
     tree = cKDTree(np.stack([x, y], axis=1))
@@ -327,16 +373,14 @@ def enrich_half_planes(x, y, nx, ny, kind, ptr, idx, cap, min_quality=1e-4, min_
     nptr = np.zeros(x.shape[0] + 1, dtype=np.int64)
     np.cumsum(counts, out=nptr[1:])
     nidx = np.empty(nptr[-1], dtype=np.int32)
-    keep = np.ones(x.shape[0], dtype=bool)
-    keep[bad] = False
-    # copy untouched rows in bulk, then the repaired ones
-    owner = np.repeat(np.arange(x.shape[0]), np.diff(ptr))
-    src_rows = keep[owner]
-    dst = np.repeat(nptr[:-1] - ptr[:-1], np.diff(ptr)) + np.arange(idx.shape[0])
-    nidx[dst[src_rows]] = idx[src_rows]
+    # untouched rows between repaired ones are copied as blocks (bad is sorted)
+    nxt = 0
     for p in bad:
         p = int(p)
+        nidx[nptr[nxt]:nptr[p]] = idx[ptr[nxt]:ptr[p]]
         nidx[nptr[p]:nptr[p + 1]] = lists[p]
+        nxt = p + 1
+    nidx[nptr[nxt]:] = idx[ptr[nxt]:]
     return nptr.astype(np.int32), nidx
 
 
@@ -351,41 +395,50 @@ def _in_half(v, h):
         return dn * dn > tie and dn < 0
     return dn * dn > tie and dn > 0
 
-def lattice_box_neighbours(x, y, ns, nr, k, cap, tie_key=None):
+def lattice_box_neighbours(x, y, ns, nr, k, cap, tie_key=None, chunk=1 << 20, progress=None):
     """Neighbours of lattice point (i, j): every (i+a mod ns, j+b) with
     |a|, |b| <= k, b inside the layer range, sorted by distance, ties by layer
     offset b and then by the station offset a signed by the side of the
     x axis the point lies on (so mirror images list mirrored neighbours in
     the same order); at most `cap` (those strictly closer than the first one
-    dropped)."""
+    dropped).  Points are processed in chunks of `chunk`."""
     n = ns * nr
-    p = np.arange(n)
-    ip, jp = p % ns, p // ns
-    side = np.where(y < 0.0, -1, 1)
     offs = np.array([(a, b) for b in range(-k, k + 1) for a in range(-k, k + 1) if (a, b) != (0, 0)])
     m = offs.shape[0]
     # per side, offsets pre-ordered by the tie key (b, side * a)
     order_up = np.lexsort((offs[:, 0], offs[:, 1]))
     order_lo = np.lexsort((-offs[:, 0], offs[:, 1]))
-    A = np.where(side[:, None] > 0, offs[order_up, 0][None, :], offs[order_lo, 0][None, :])
-    B = np.where(side[:, None] > 0, offs[order_up, 1][None, :], offs[order_lo, 1][None, :])
-    jn = jp[:, None] + B
-    valid = (jn >= 0) & (jn < nr)
-    cols = np.where(valid, jn, 0) * ns + (ip[:, None] + A) % ns
-    dx = x[cols] - x[:, None]
-    dy = y[cols] - y[:, None]
-    d2 = np.where(valid, dx * dx + dy * dy, np.inf)
-    o = np.argsort(d2, axis=1, kind="stable")
-    d2 = np.take_along_axis(d2, o, axis=1)
-    cols = np.take_along_axis(cols, o, axis=1)
-    keep = np.isfinite(d2)
-    if m > cap:
-        cut = d2[:, cap][:, None]
-        keep &= ~np.isfinite(cut) | (d2 < cut)
-    counts = keep.sum(axis=1)
+    a_up, b_up = offs[order_up, 0][None, :], offs[order_up, 1][None, :]
+    a_lo, b_lo = offs[order_lo, 0][None, :], offs[order_lo, 1][None, :]
+    counts = np.empty(n, dtype=np.int64)
+    parts = []
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        p = np.arange(lo, hi)
+        ip, jp = p % ns, p // ns
+        up = (np.where(y[lo:hi] < 0.0, -1, 1) > 0)[:, None]
+        A = np.where(up, a_up, a_lo)
+        B = np.where(up, b_up, b_lo)
+        jn = jp[:, None] + B
+        valid = (jn >= 0) & (jn < nr)
+        cols = np.where(valid, jn, 0) * ns + (ip[:, None] + A) % ns
+        dx = x[cols] - x[lo:hi, None]
+        dy = y[cols] - y[lo:hi, None]
+        d2 = np.where(valid, dx * dx + dy * dy, np.inf)
+        o = np.argsort(d2, axis=1, kind="stable")
+        d2 = np.take_along_axis(d2, o, axis=1)
+        cols = np.take_along_axis(cols, o, axis=1)
+        keep = np.isfinite(d2)
+        if m > cap:
+            cut = d2[:, cap][:, None]
+            keep &= ~np.isfinite(cut) | (d2 < cut)
+        counts[lo:hi] = keep.sum(axis=1)
+        parts.append(cols[keep].astype(np.int32))
+        if progress is not None:
+            progress(f"lattice neighbours {hi}/{n}")
     ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=ptr[1:])
-    return ptr.astype(np.int32), cols[keep].astype(np.int32)
+    return ptr.astype(np.int32), np.concatenate(parts)
 
 
 def _mirror_tie_key(ii, jj, ns, y):

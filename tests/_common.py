@@ -45,3 +45,64 @@ def cloud(name):
         else:
             raise KeyError(name)
     return _CLOUDS[name]
+
+
+def dependency_subcloud(c, centres, depth):
+    """The points reachable from `centres` in at most `depth` hops along each
+    point's own neighbour list, as a cloud of their own.
+
+    Points fewer than `depth` hops out keep their full lists in the stored
+    order.  The outermost ring is made of outer (held) points; what they
+    compute never reaches a centre, so their lists only have to be valid
+    stencils: every other member within two hops, in index order (the
+    members among their own neighbours alone can be one-sided or collinear).
+    Every value the method computes at a centre that depends on the state
+    only within depth - 1 hops (q-derivatives after k inner iterations reach
+    k + 1 hops, the flux residual k + 2) is then the same computation on the
+    sub-cloud as on the whole cloud.  Returns the sub-cloud, the member
+    indices (ascending, the sub-cloud's point order) and the sub-cloud index
+    of each centre."""
+    from cloudgen import Cloud, KIND_OUTER
+    ptr, idx = c.nbr_ptr, c.nbr_idx
+    hop = np.full(c.n, -1, dtype=np.int8)
+    front = np.unique(np.asarray(centres, dtype=np.int64))
+    hop[front] = 0
+    for r in range(1, depth + 1):
+        nb = np.unique(np.concatenate([idx[ptr[p]:ptr[p + 1]] for p in front]))
+        nb = nb[hop[nb] < 0]
+        hop[nb] = r
+        front = nb
+    members = np.flatnonzero(hop >= 0)
+    lists, kind = [], c.kind[members].copy()
+    for k, p in enumerate(members):
+        nb = idx[ptr[p]:ptr[p + 1]]
+        if hop[p] == depth:
+            two = np.concatenate([nb] + [idx[ptr[i]:ptr[i + 1]] for i in nb])
+            two = np.unique(two[hop[two] >= 0])
+            nb = two[two != p]
+            kind[k] = KIND_OUTER
+        lists.append(np.searchsorted(members, nb))
+    sptr = np.zeros(members.size + 1, dtype=np.int32)
+    np.cumsum([len(v) for v in lists], out=sptr[1:])
+    sub = Cloud(x=c.x[members], y=c.y[members], nx=c.nx[members], ny=c.ny[members], kind=kind,
+                nbr_ptr=sptr, nbr_idx=np.concatenate(lists).astype(np.int32))
+    return sub, members, np.searchsorted(members, np.asarray(centres, dtype=np.int64))
+
+
+def sample_points(c, count, seed):
+    """Seeded sample of points for checks at full size: `count` uniformly
+    drawn points plus the wall and next-to-outer points at the trailing and
+    leading edges and the points with the longest neighbour lists."""
+    from cloudgen import uniform01
+    n = c.n
+    pick = np.minimum((uniform01(seed, count) * n).astype(np.int64), n - 1)
+    special = []
+    ns = c.meta.get("ns")
+    nr = c.meta.get("nr")
+    if ns and nr:
+        for i in (0, 1, ns // 2, ns - 1):
+            for j in (0, 1, nr // 2, nr - 2):
+                special.append(j * ns + i)
+    deg = np.diff(c.nbr_ptr)
+    special.extend(np.argsort(deg, kind="stable")[-8:].tolist())
+    return np.unique(np.concatenate([pick, np.array(special, dtype=np.int64)]))

@@ -14,11 +14,14 @@ folds the least-squares solve into per-neighbour weights) and libm vs
 device-library transcendentals, all at the level of a few ulp per
 operation.
 """
+import os
+
 import numpy as np
 import pytest
 
 import oracle
-from tests._common import cloud, normwise_rel, smooth_state
+from tests._common import (cloud, dependency_subcloud, normwise_rel, sample_points,
+                           smooth_state)
 
 pytestmark = pytest.mark.gpu
 
@@ -219,6 +222,47 @@ def test_c2_full_size_evaluate(ql):
     for key in ("q", "g", "R", "dt"):
         floor = normwise_rel(ora_fma[key], ora[key])
         err = normwise_rel(gpu[key], ora[key])
+        _say(f"  {key}: gpu {err.max():.2e}  floor {floor.max():.2e}")
+        assert np.all(err <= 10.0 * floor + 1e-14), (key, err, floor)
+
+
+@pytest.mark.skipif(not os.environ.get("QL_NACA40M"),
+                    reason="the 40M-point cloud takes minutes to build; set QL_NACA40M to a "
+                           ".npz path (the cloud is cached there) to run this check")
+@pytest.mark.timeout(1100)
+def test_c5_sampled_evaluate(ql):
+    """40M-point cloud (5000 x 8000, interior jittered as the 2.5M cloud),
+    M 0.85, alpha 1, limiter on: flags bit-exact against the oracle's
+    classification of the whole cloud; one evaluation of the stage operator
+    on the whole cloud on the GPU, compared at a seeded sample of points
+    (uniform draws plus the trailing- and leading-edge wall and near-outer
+    points and the longest neighbour lists) with the oracle evaluated on each
+    sample's dependency sub-cloud (n_inner + 2 neighbour hops, which gives
+    the whole-cloud values bit for bit), within 10x the FMA-contraction noise
+    floor as in the 2.5M check."""
+    from cloudgen import naca_ocloud_cached
+    _say("c5 sampled evaluate")
+    c = naca_ocloud_cached(os.environ["QL_NACA40M"], 5000, 8000, jitter=0.1, seed=2108,
+                           progress=_say)
+    prm = dict(limiter=1, mach=0.85, alpha_deg=1.0)
+    o, s = _pair(ql, c, **prm)
+    np.testing.assert_array_equal(s.flags(), o.flag)
+    del o
+    _say("  flags bit-exact")
+    U = smooth_state(c, mach=0.85, alpha_deg=1.0)
+    s.set_state(U)
+    gpu = s.evaluate()
+    s.close()
+    centres = sample_points(c, 320, seed=5)
+    sub, members, where = dependency_subcloud(c, centres, oracle.params()["n_inner"] + 2)
+    _say(f"  {centres.size} samples, sub-clouds {sub.n} points")
+    ora = oracle.Oracle(sub, oracle.params(**prm)).evaluate(U[:, members])
+    ora_fma = oracle.Oracle(sub, oracle.params(**prm),
+                            lib=oracle.load(oracle.FMA_LIB)).evaluate(U[:, members])
+    for key in ("q", "g", "R", "dt", "qmax", "qmin"):
+        ref = np.atleast_2d(ora[key])[:, where]
+        floor = normwise_rel(np.atleast_2d(ora_fma[key])[:, where], ref)
+        err = normwise_rel(np.atleast_2d(gpu[key])[:, centres], ref)
         _say(f"  {key}: gpu {err.max():.2e}  floor {floor.max():.2e}")
         assert np.all(err <= 10.0 * floor + 1e-14), (key, err, floor)
 
