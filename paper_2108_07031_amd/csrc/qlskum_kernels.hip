@@ -693,8 +693,21 @@ struct Prim {
     double rho, u1, u2, p, sqb, isqb, rhoe;
 };
 
+// 1/d from the hardware reciprocal estimate refined by two Newton steps
+// (each squares the relative error; the result is within an ulp or two of
+// the rounded quotient) for d normal and finite -- the flux body's divisors
+// (2 beta of a state that passes the positivity check, the limiter's
+// denominator, which is zero or at least eps^2) are.  A correctly rounded
+// division costs several times more issue slots in this VALU-bound kernel.
+__device__ __forceinline__ double fast_rcp(double d) {
+#pragma clang fp contract(off)
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return fma(r, fma(-d, r, 1.0), r);
+}
+
 // q~ -> primitive state (inverse of eq. (26)); false if q4 >= 0 or the
-// result is not finite (the Maxwellian of q~ does not exist).  One division
+// result is not finite (the Maxwellian of q~ does not exist).  One reciprocal
 // (1/(2 beta)), one square root and one exponential: 1/sqrt(beta) =
 // 2 sqrt(beta) / (2 beta), and beta^(-1/(gamma-1)) = (1/sqrt(beta))^m.
 // The per-state formulas below are written with explicit fma and no implicit
@@ -704,7 +717,7 @@ template <int POW>
 __device__ __forceinline__ bool q_to_prim(const double qt[4], const FlowParams &fp, Prim &s) {
 #pragma clang fp contract(off)
     const double beta = -0.5 * qt[3];
-    const double inv2b = -1.0 / qt[3];
+    const double inv2b = -fast_rcp(qt[3]);
     s.u1 = qt[1] * inv2b;
     s.u2 = qt[2] * inv2b;
     const double uu = fma(s.u1, s.u1, s.u2 * s.u2);
@@ -758,7 +771,7 @@ __device__ __forceinline__ double venkat(double delta, double q, double qmx, dou
     const double a = fma(D, D, eps2);
     const double num = fma(2.0 * delta, D, a);
     const double den = fma(delta, D, fma(2.0 * delta, delta, a));
-    return (den == 0.0) ? 1.0 : num / den;
+    return (den == 0.0) ? 1.0 : num * fast_rcp(den);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
