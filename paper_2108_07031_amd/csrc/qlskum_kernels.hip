@@ -750,7 +750,7 @@ __device__ __forceinline__ void split_flux(const Prim &s, double ex, double ey, 
     const double ue = fma(s.u1, ex, s.u2 * ey);
     const double S = ue * s.sqb;
     const double E = gauss(S);
-    const double A = half_erfc(-sg * S, E);
+    const double A = half_erfc(-sg * S, E, fast_rcp(kErfcC64 + fabs(S)));
     const double B = (E * kHalfRsqrtPi) * s.isqb;
     const double sB = sg * B;
     const double mass = s.rho * fma(ue, A, sB);
@@ -1140,7 +1140,7 @@ __device__ __forceinline__ void split_flux_f(const PrimF &s, float ex, float ey,
     const float ue = fmaf(s.u1, ex, s.u2 * ey);
     const float S = ue * s.sqb;
     const float E = __expf(-(S * S));
-    const float A = half_erfc_f(-sg * S, E);
+    const float A = half_erfc_f(-sg * S, E, __builtin_amdgcn_rcpf(kErfcC32 + fabsf(S)));
     const float B = (E * kHalfRsqrtPi) * s.isqb;
     const float sB = sg * B;
     const float mass = s.rho * fmaf(ue, A, sB);
