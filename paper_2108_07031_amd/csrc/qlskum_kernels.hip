@@ -706,10 +706,20 @@ __device__ __forceinline__ double fast_rcp(double d) {
     return fma(r, fma(-d, r, 1.0), r);
 }
 
+// 1/sqrt(d) from the hardware estimate refined by two Newton steps
+// r <- r + (r/2)(1 - d r^2), for d positive, normal and finite (beta of a
+// state that passes the positivity check).
+__device__ __forceinline__ double fast_rsqrt(double d) {
+#pragma clang fp contract(off)
+    double r = __builtin_amdgcn_rsq(d);
+    r = fma(0.5 * r, fma(-(d * r), r, 1.0), r);
+    return fma(0.5 * r, fma(-(d * r), r, 1.0), r);
+}
+
 // q~ -> primitive state (inverse of eq. (26)); false if q4 >= 0 or the
 // result is not finite (the Maxwellian of q~ does not exist).  One reciprocal
-// (1/(2 beta)), one square root and one exponential: 1/sqrt(beta) =
-// 2 sqrt(beta) / (2 beta), and beta^(-1/(gamma-1)) = (1/sqrt(beta))^m.
+// (1/(2 beta)), one reciprocal square root and one exponential:
+// sqrt(beta) = beta / sqrt(beta), and beta^(-1/(gamma-1)) = (1/sqrt(beta))^m.
 // The per-state formulas below are written with explicit fma and no implicit
 // contraction, so that two reconstructed states that are bitwise equal give
 // bitwise equal fluxes (uniform flow keeps R = 0 exactly).
@@ -721,15 +731,15 @@ __device__ __forceinline__ bool q_to_prim(const double qt[4], const FlowParams &
     s.u1 = qt[1] * inv2b;
     s.u2 = qt[2] * inv2b;
     const double uu = fma(s.u1, s.u1, s.u2 * s.u2);
-    s.sqb = sqrt(beta);
-    s.isqb = (2.0 * s.sqb) * inv2b;
+    s.isqb = fast_rsqrt(beta);
+    s.sqb = beta * s.isqb;
     if (POW > 0) {
         double pw = s.isqb;
 #pragma unroll
         for (int j = 1; j < POW; ++j) pw *= s.isqb;
-        s.rho = exp(fma(beta, uu, qt[0])) * pw;
+        s.rho = exp_poly(fma(beta, uu, qt[0])) * pw;
     } else {
-        s.rho = exp(fma(beta, uu, fma(-log(beta), fp.gm1inv, qt[0])));
+        s.rho = exp_poly(fma(beta, uu, fma(-log(beta), fp.gm1inv, qt[0])));
     }
     s.p = s.rho * inv2b;
     s.rhoe = fma(s.p, fp.gm1inv, (0.5 * s.rho) * uu);
