@@ -82,8 +82,8 @@ hipError_t launch_unpermute_state(hipStream_t st, int n, const double *U, const 
 hipError_t launch_prep(hipStream_t st, const DevCloud &c, const FlowParams &fp, const double *U,
                        double *Un, double2 *q, double *dt, float4 *q32, int *err);
 // q-derivatives (tiled like the flux sweep; lds_budget as there): first
-// pass with limiter bounds, and one inner iteration from the first pass g0
-// and the previous iterate gprev.
+// pass with the limiter bounds (qmm: qmax - q and qmin - q per point), and
+// one inner iteration from the first pass g0 and the previous iterate gprev.
 hipError_t launch_grad0(hipStream_t st, const DevCloud &c, int lds_budget, const double2 *q,
                         double2 *g, double2 *qmm, int want_bounds, Shadow sh);
 hipError_t launch_gradk(hipStream_t st, const DevCloud &c, int lds_budget, const double2 *g0,

@@ -444,7 +444,8 @@ __device__ __forceinline__ int slot_point(const DevCloud &cl, const TileInfo &ti
 
 // first pass: full-stencil least squares of dq_i = q_i - q_p (eq. (11)), and
 // the componentwise max / min of q over the point and its stencil (bounds of
-// the limited reconstruction).  Slot record (double2): q 0..1, position 2.
+// the limited reconstruction), stored as offsets from q.  Slot record
+// (double2): q 0..1, position 2.
 __global__ void __launch_bounds__(kBlock) k_grad0(DevCloud cl, int cap,
                                                   const double2 *__restrict__ q,
                                                   double2 *__restrict__ g,
@@ -527,7 +528,21 @@ __global__ void __launch_bounds__(kBlock) k_grad0(DevCloud cl, int cap,
     g[4 * p + sub] = make_double2(gv[2 * sub], gv[2 * sub + 1]);
     if (sh.g32 && sub < 2) sh.g32[2 * p + sub] = to_f4(gv + 4 * sub);
     if (want_bounds) {
-        const double bv[8] = {mx[0], mx[1], mx[2], mx[3], mn[0], mn[1], mn[2], mn[3]};
+        // bounds are stored as offsets from q (the limiter's D = q_max - q or
+        // q_min - q, the same FP64 subtraction it would make per entry)
+        double qp[4];
+        if (ti.in_lds) {
+            const double2 *r = lds + kRec * j;
+            qp[0] = r[0].x; qp[1] = r[0].y; qp[2] = r[1].x; qp[3] = r[1].y;
+        } else {
+            load4(q, p, qp);
+        }
+        double bv[8];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            bv[r] = mx[r] - qp[r];
+            bv[4 + r] = mn[r] - qp[r];
+        }
         qmm[4 * p + sub] = make_double2(bv[2 * sub], bv[2 * sub + 1]);
         if (sh.qmm32 && sub < 2) sh.qmm32[2 * p + sub] = to_f4(bv + 4 * sub);
     }
@@ -716,6 +731,16 @@ __device__ __forceinline__ double fast_rsqrt(double d) {
     return fma(0.5 * r, fma(-(d * r), r, 1.0), r);
 }
 
+// sqrt(d) for d positive, normal and finite: s = d r with r the hardware
+// 1/sqrt estimate, then one Newton correction s + (d - s^2) r/2, which
+// squares the estimate's relative error.
+__device__ __forceinline__ double fast_sqrt(double d) {
+#pragma clang fp contract(off)
+    const double r = __builtin_amdgcn_rsq(d);
+    const double s = d * r;
+    return fma(fma(-s, s, d), 0.5 * r, s);
+}
+
 // q~ -> primitive state (inverse of eq. (26)); false if q4 >= 0 or the
 // result is not finite (the Maxwellian of q~ does not exist).  One reciprocal
 // (1/(2 beta)), one reciprocal square root and one exponential:
@@ -773,11 +798,11 @@ __device__ __forceinline__ void split_flux(const Prim &s, double ex, double ey, 
 
 // Venkatakrishnan limiter value for the increment delta of one component:
 //   phi = (D^2 + eps^2 + 2 delta D) / (D^2 + 2 delta^2 + delta D + eps^2)
-// with D = qmax - q (delta > 0) or qmin - q.
-__device__ __forceinline__ double venkat(double delta, double q, double qmx, double qmn,
-                                         double eps2) {
+// with D = qmax - q (delta > 0) or qmin - q, the point's stored offsets dmax
+// and dmin.
+__device__ __forceinline__ double venkat(double delta, double dmax, double dmin, double eps2) {
 #pragma clang fp contract(off)
-    const double D = (delta > 0.0) ? (qmx - q) : (qmn - q);
+    const double D = (delta > 0.0) ? dmax : dmin;
     const double a = fma(D, D, eps2);
     const double num = fma(2.0 * delta, D, a);
     const double den = fma(delta, D, fma(2.0 * delta, delta, a));
@@ -819,14 +844,14 @@ __device__ __forceinline__ bool flux_entry(uint8_t f, double dx, double dy, doub
             qt0[r] = qp[r];
         }
     } else if (LIMITER) {
-        const double e = fp.venkat_k * sqrt(fma(dx, dx, dy * dy));
+        const double e = fp.venkat_k * fast_sqrt(fma(dx, dx, dy * dy));
         const double eps2 = (e * e) * e;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const double di = -0.5 * fma(dx, gi[r], dy * gi[4 + r]);
             const double d0 = -0.5 * fma(dx, gp[r], dy * gp[4 + r]);
-            qti[r] = fma(venkat(di, qi[r], bi[r], bi[4 + r], eps2), di, qi[r]);
-            qt0[r] = fma(venkat(d0, qp[r], bp[r], bp[4 + r], eps2), d0, qp[r]);
+            qti[r] = fma(venkat(di, bi[r], bi[4 + r], eps2), di, qi[r]);
+            qt0[r] = fma(venkat(d0, bp[r], bp[4 + r], eps2), d0, qp[r]);
         }
     } else {
 #pragma unroll
@@ -932,7 +957,7 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevCloud cl, FlowParams fp, int
                                                  double2 *__restrict__ qnext,
                                                  double *__restrict__ Rout,
                                                  float4 *__restrict__ q32next, int *err) {
-    // slot record (double2): q 0..1, g 2..5, bounds 6..9, position last
+    // slot record (double2): q 0..1, g 2..5, bound offsets 6..9, position last
     // (first order: q and position only)
     constexpr int kRec = FIRST ? 3 : (LIMITER ? 11 : 7);
     extern __shared__ double2 lds[];
@@ -1107,7 +1132,7 @@ hipError_t launch_flux(hipStream_t st, const DevCloud &c, const FlowParams &fp, 
 // ---------------------------------------------------------------------------
 // Mixed precision flux residual + Runge-Kutta stage.  The reconstruction
 // (eq. (28)), the limiter and the split fluxes run in FP32 from the FP32
-// shadows of q, its derivatives and its bounds, using the hardware FP32
+// shadows of q, its derivatives and its bound offsets, using the hardware FP32
 // exp / sqrt / reciprocal; the geometry, the least-squares weights, the
 // residual sums and the state update stay FP64.  Same tiling and lane
 // layout as k_flux; the LDS image holds the FP32 records (16-byte q, 32-byte
@@ -1123,12 +1148,12 @@ template <int POW>
 __device__ __forceinline__ bool q_to_prim_f(const float qt[4], float gm1inv, PrimF &s) {
 #pragma clang fp contract(off)
     const float beta = -0.5f * qt[3];
-    const float inv2b = -1.0f / qt[3];
+    const float inv2b = -__builtin_amdgcn_rcpf(qt[3]);
     s.u1 = qt[1] * inv2b;
     s.u2 = qt[2] * inv2b;
     const float uu = fmaf(s.u1, s.u1, s.u2 * s.u2);
-    s.sqb = sqrtf(beta);
-    s.isqb = (2.0f * s.sqb) * inv2b;
+    s.isqb = __builtin_amdgcn_rsqf(beta);
+    s.sqb = beta * s.isqb;
     if (POW > 0) {
         float pw = s.isqb;
 #pragma unroll
@@ -1161,13 +1186,13 @@ __device__ __forceinline__ void split_flux_f(const PrimF &s, float ex, float ey,
     G[3] = fmaf((s.p + s.rhoe) * ue, A, (fmaf(0.5f, s.p, s.rhoe)) * sB);
 }
 
-__device__ __forceinline__ float venkat_f(float delta, float q, float qmx, float qmn, float eps2) {
+__device__ __forceinline__ float venkat_f(float delta, float dmax, float dmin, float eps2) {
 #pragma clang fp contract(off)
-    const float D = (delta > 0.0f) ? (qmx - q) : (qmn - q);
+    const float D = (delta > 0.0f) ? dmax : dmin;
     const float a = fmaf(D, D, eps2);
     const float num = fmaf(2.0f * delta, D, a);
     const float den = fmaf(delta, D, fmaf(2.0f * delta, delta, a));
-    return (den == 0.0f) ? 1.0f : num / den;
+    return (den == 0.0f) ? 1.0f : num * __builtin_amdgcn_rcpf(den);
 }
 
 __device__ __forceinline__ void unpack(const float4 a, float *v) {
@@ -1195,14 +1220,14 @@ __device__ __forceinline__ bool flux_entry_f(uint8_t f, double dx, double dy, do
             qt0[r] = qp[r];
         }
     } else if (LIMITER) {
-        const float e = vk * sqrtf(fmaf(dxf, dxf, dyf * dyf));
+        const float e = vk * __builtin_amdgcn_sqrtf(fmaf(dxf, dxf, dyf * dyf));
         const float eps2 = (e * e) * e;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const float di = -0.5f * fmaf(dxf, gi[r], dyf * gi[4 + r]);
             const float d0 = -0.5f * fmaf(dxf, gp[r], dyf * gp[4 + r]);
-            qti[r] = fmaf(venkat_f(di, qi[r], bi[r], bi[4 + r], eps2), di, qi[r]);
-            qt0[r] = fmaf(venkat_f(d0, qp[r], bp[r], bp[4 + r], eps2), d0, qp[r]);
+            qti[r] = fmaf(venkat_f(di, bi[r], bi[4 + r], eps2), di, qi[r]);
+            qt0[r] = fmaf(venkat_f(d0, bp[r], bp[4 + r], eps2), d0, qp[r]);
         }
     } else {
 #pragma unroll

@@ -1011,12 +1011,17 @@ int ql_debug_fetch(ql_solver *s, int32_t what, double *out) {
         for (int q = 0; q < n; ++q) out[s->perm[q]] = h[q];
         break;
     case 4:
-    case 5:
+    case 5: {
+        // the bounds are held as offsets from q: q + (qmax - q), within an ulp of qmax
+        if ((st = get(s->q[s->qcur], (size_t)4 * n))) return st;
+        const std::vector<double> hq = h;
         if ((st = get(s->qmm, (size_t)8 * n))) return st;
         for (int q = 0; q < n; ++q)
             for (int r = 0; r < 4; ++r)
-                out[(size_t)r * n + s->perm[q]] = h[(size_t)8 * q + (what == 4 ? 0 : 4) + r];
+                out[(size_t)r * n + s->perm[q]] =
+                    hq[(size_t)4 * q + r] + h[(size_t)8 * q + (what == 4 ? 0 : 4) + r];
         break;
+    }
     }
     return QL_OK;
 }
