@@ -125,10 +125,11 @@ WARM = dict(ns=64, nr=24, n_train=48, n_test=8, seed_train=1, seed_test=2, drop=
             lr=2e-3, floor=0.05)
 
 
-# Batched form: independent clouds of log-uniform sizes advanced by the same
-# launches (one captured iteration replayed), against the same clouds run
-# one after the other.
-BATCH = dict(n_case=16, n_lo=20000, n_hi=160000, seed=7031, iters=200)
+# Batched form: 64 independent clouds of log-uniform sizes in [40k, 640k]
+# points, each with its own flow condition, advanced by the same launches
+# (one captured iteration replayed) in mixed precision with the limiter,
+# against the same clouds run one after the other.
+BATCH = dict(n_case=64, n_lo=40000, n_hi=640000, seed=7031, iters=200, precision=1)
 
 
 def batch_study():
@@ -145,7 +146,8 @@ def batch_study():
         clouds.append(naca_ocloud(ns, int(round(nn / ns)), tau=c["tau"], jitter=0.1,
                                   seed=B["seed"] + 10 + k))
     total = sum(cl.n for cl in clouds)
-    prm = dict(limiter=1)
+    prm = dict(limiter=1, precision=B["precision"])
+    log(f"  {B['n_case']} clouds, {total} points")
     s = ql.Solver(**prm)
     s.upload_batch(clouds, [c["mach"] for c in conds], [c["alpha"] for c in conds])
     s.init_freestream()
@@ -166,7 +168,7 @@ def batch_study():
         torch.cuda.synchronize()
         t_solo += time.perf_counter() - t0
         so.close()
-    return {"cases": B["n_case"], "points_total": total,
+    return {"cases": B["n_case"], "points_total": total, "precision": PREC_NAME[B["precision"]],
             "points_min_max": [min(cl.n for cl in clouds), max(cl.n for cl in clouds)],
             "iterations": B["iters"],
             "batched_mpt_it_s": total * B["iters"] / t_batch / 1e6,
