@@ -799,14 +799,16 @@ __device__ __forceinline__ void split_flux(const Prim &s, double ex, double ey, 
 // Venkatakrishnan limiter value for the increment delta of one component:
 //   phi = (D^2 + eps^2 + 2 delta D) / (D^2 + 2 delta^2 + delta D + eps^2)
 // with D = qmax - q (delta > 0) or qmin - q, the point's stored offsets dmax
-// and dmin.
+// and dmin.  The denominator is (D + delta/2)^2 + 7/4 delta^2 + eps^2 >=
+// eps^2 > 0: callers keep eps^2 at least 1e-300, so that coincident points
+// (D = delta = eps = 0, the one 0/0 case) give phi = 1 without a test here.
 __device__ __forceinline__ double venkat(double delta, double dmax, double dmin, double eps2) {
 #pragma clang fp contract(off)
     const double D = (delta > 0.0) ? dmax : dmin;
     const double a = fma(D, D, eps2);
     const double num = fma(2.0 * delta, D, a);
     const double den = fma(delta, D, fma(2.0 * delta, delta, a));
-    return (den == 0.0) ? 1.0 : num * fast_rcp(den);
+    return num * fast_rcp(den);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -845,7 +847,7 @@ __device__ __forceinline__ bool flux_entry(uint8_t f, double dx, double dy, doub
         }
     } else if (LIMITER) {
         const double e = fp.venkat_k * fast_sqrt(fma(dx, dx, dy * dy));
-        const double eps2 = (e * e) * e;
+        const double eps2 = fmax((e * e) * e, 1e-300);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const double di = -0.5 * fma(dx, gi[r], dy * gi[4 + r]);
@@ -1186,13 +1188,14 @@ __device__ __forceinline__ void split_flux_f(const PrimF &s, float ex, float ey,
     G[3] = fmaf((s.p + s.rhoe) * ue, A, (fmaf(0.5f, s.p, s.rhoe)) * sB);
 }
 
+// FP32 counterpart of venkat (eps^2 kept at least 1e-30 by the caller)
 __device__ __forceinline__ float venkat_f(float delta, float dmax, float dmin, float eps2) {
 #pragma clang fp contract(off)
     const float D = (delta > 0.0f) ? dmax : dmin;
     const float a = fmaf(D, D, eps2);
     const float num = fmaf(2.0f * delta, D, a);
     const float den = fmaf(delta, D, fmaf(2.0f * delta, delta, a));
-    return (den == 0.0f) ? 1.0f : num * __builtin_amdgcn_rcpf(den);
+    return num * __builtin_amdgcn_rcpf(den);
 }
 
 __device__ __forceinline__ void unpack(const float4 a, float *v) {
@@ -1221,7 +1224,7 @@ __device__ __forceinline__ bool flux_entry_f(uint8_t f, double dx, double dy, do
         }
     } else if (LIMITER) {
         const float e = vk * __builtin_amdgcn_sqrtf(fmaf(dxf, dxf, dyf * dyf));
-        const float eps2 = (e * e) * e;
+        const float eps2 = fmaxf((e * e) * e, 1e-30f);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const float di = -0.5f * fmaf(dxf, gi[r], dyf * gi[4 + r]);
