@@ -664,7 +664,7 @@ __global__ void __launch_bounds__(kBlock) k_gradk(DevCloud cl, int cap,
         const double ls = (c < 4) ? fma(L0, sx[r], -(L1 * sy[r])) : fma(L2, sy[r], -(L1 * sx[r]));
         v[m] = fma(-0.5, ls - (m == 0 ? gq.x : gq.y), m == 0 ? z.x : z.y);
     }
-    gnext[4 * p + sub] = make_double2(v[0], v[1]);
+    if (gnext) gnext[4 * p + sub] = make_double2(v[0], v[1]);
     if (g32) {
         // the FP32 shadow packs (q_x[0..3]) and (q_y[0..3]): lanes 0,1 and 2,3
         // hold halves of one float4, combined through a shuffle of partner lanes
@@ -704,8 +704,25 @@ hipError_t launch_gradk(hipStream_t st, const DevCloud &c, int lds_budget, const
 // ---------------------------------------------------------------------------
 namespace {
 
+// x^K by repeated squaring (x^5 = (x^2)^2 x: three multiplications)
+template <int K, class T>
+__device__ __forceinline__ T ipow(T x) {
+    if constexpr (K == 1) {
+        return x;
+    } else if constexpr (K % 2 == 0) {
+        const T h = ipow<K / 2>(x);
+        return h * h;
+    } else {
+        return ipow<K - 1>(x) * x;
+    }
+}
+
+constexpr double kHalfRsqrtPi = 0.28209479177387814347;  // 1 / (2 sqrt(pi))
+
+// primitive state with the per-state factors of the split fluxes:
+// bk = 1/(2 sqrt(pi beta)), h = p + rho e, k = p/2 + rho e
 struct Prim {
-    double rho, u1, u2, p, sqb, isqb, rhoe;
+    double rho, u1, u2, p, sqb, bk, h, k;
 };
 
 // 1/d from the hardware reciprocal estimate refined by two Newton steps
@@ -756,18 +773,18 @@ __device__ __forceinline__ bool q_to_prim(const double qt[4], const FlowParams &
     s.u1 = qt[1] * inv2b;
     s.u2 = qt[2] * inv2b;
     const double uu = fma(s.u1, s.u1, s.u2 * s.u2);
-    s.isqb = fast_rsqrt(beta);
-    s.sqb = beta * s.isqb;
+    const double isqb = fast_rsqrt(beta);
+    s.sqb = beta * isqb;
     if (POW > 0) {
-        double pw = s.isqb;
-#pragma unroll
-        for (int j = 1; j < POW; ++j) pw *= s.isqb;
-        s.rho = exp_poly(fma(beta, uu, qt[0])) * pw;
+        s.rho = exp_poly(fma(beta, uu, qt[0])) * ipow<POW>(isqb);
     } else {
         s.rho = exp_poly(fma(beta, uu, fma(-log(beta), fp.gm1inv, qt[0])));
     }
     s.p = s.rho * inv2b;
-    s.rhoe = fma(s.p, fp.gm1inv, (0.5 * s.rho) * uu);
+    const double rhoe = fma(s.p, fp.gm1inv, (0.5 * s.rho) * uu);
+    s.h = s.p + rhoe;
+    s.k = fma(0.5, s.p, rhoe);
+    s.bk = kHalfRsqrtPi * isqb;
     return (qt[3] < 0.0) && isfinite(s.rho) && isfinite(s.p) && isfinite(s.u1) &&
            isfinite(s.u2);
 }
@@ -781,19 +798,18 @@ __device__ __forceinline__ bool q_to_prim(const double qt[4], const FlowParams &
 __device__ __forceinline__ void split_flux(const Prim &s, double ex, double ey, double sg,
                                            double G[4]) {
 #pragma clang fp contract(off)
-    constexpr double kHalfRsqrtPi = 0.28209479177387814347;  // 1 / (2 sqrt(pi))
     const double ue = fma(s.u1, ex, s.u2 * ey);
     const double S = ue * s.sqb;
     const double E = gauss(S);
     const double A = half_erfc(-sg * S, E, fast_rcp(kErfcC64 + fabs(S)));
-    const double B = (E * kHalfRsqrtPi) * s.isqb;
+    const double B = E * s.bk;
     const double sB = sg * B;
     const double mass = s.rho * fma(ue, A, sB);
     const double pA = s.p * A;
     G[0] = mass;
     G[1] = fma(s.u1, mass, pA * ex);
     G[2] = fma(s.u2, mass, pA * ey);
-    G[3] = fma((s.p + s.rhoe) * ue, A, (fma(0.5, s.p, s.rhoe)) * sB);
+    G[3] = fma(s.h * ue, A, s.k * sB);
 }
 
 // Venkatakrishnan limiter value for the increment delta of one component:
@@ -848,10 +864,13 @@ __device__ __forceinline__ bool flux_entry(uint8_t f, double dx, double dy, doub
     } else if (LIMITER) {
         const double e = fp.venkat_k * fast_sqrt(fma(dx, dx, dy * dy));
         const double eps2 = fmax((e * e) * e, 1e-300);
+        // -1/2 folded into the offsets: scaling by a power of two commutes
+        // with rounding, so delta has the same bits as -1/2 (d . g)
+        const double hx = -0.5 * dx, hy = -0.5 * dy;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const double di = -0.5 * fma(dx, gi[r], dy * gi[4 + r]);
-            const double d0 = -0.5 * fma(dx, gp[r], dy * gp[4 + r]);
+            const double di = fma(hx, gi[r], hy * gi[4 + r]);
+            const double d0 = fma(hx, gp[r], hy * gp[4 + r]);
             qti[r] = fma(venkat(di, bi[r], bi[4 + r], eps2), di, qi[r]);
             qt0[r] = fma(venkat(d0, bp[r], bp[4 + r], eps2), d0, qp[r]);
         }
@@ -1157,10 +1176,7 @@ __device__ __forceinline__ bool q_to_prim_f(const float qt[4], float gm1inv, Pri
     s.isqb = __builtin_amdgcn_rsqf(beta);
     s.sqb = beta * s.isqb;
     if (POW > 0) {
-        float pw = s.isqb;
-#pragma unroll
-        for (int j = 1; j < POW; ++j) pw *= s.isqb;
-        s.rho = __expf(fmaf(beta, uu, qt[0])) * pw;
+        s.rho = __expf(fmaf(beta, uu, qt[0])) * ipow<POW>(s.isqb);
     } else {
         s.rho = __expf(fmaf(beta, uu, fmaf(-__logf(beta), gm1inv, qt[0])));
     }
@@ -1225,10 +1241,11 @@ __device__ __forceinline__ bool flux_entry_f(uint8_t f, double dx, double dy, do
     } else if (LIMITER) {
         const float e = vk * __builtin_amdgcn_sqrtf(fmaf(dxf, dxf, dyf * dyf));
         const float eps2 = fmaxf((e * e) * e, 1e-30f);
+        const float hx = -0.5f * dxf, hy = -0.5f * dyf;  // as in flux_entry
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const float di = -0.5f * fmaf(dxf, gi[r], dyf * gi[4 + r]);
-            const float d0 = -0.5f * fmaf(dxf, gp[r], dyf * gp[4 + r]);
+            const float di = fmaf(hx, gi[r], hy * gi[4 + r]);
+            const float d0 = fmaf(hx, gp[r], hy * gp[4 + r]);
             qti[r] = fmaf(venkat_f(di, bi[r], bi[4 + r], eps2), di, qi[r]);
             qt0[r] = fmaf(venkat_f(d0, bp[r], bp[4 + r], eps2), d0, qp[r]);
         }

@@ -388,14 +388,17 @@ constexpr int kGrad0Lds = 32 * 1024;
 constexpr int kGradkLds = 22 * 1024;
 
 // One stage's q-derivatives: first pass + n_inner Jacobi iterations; leaves
-// the final iterate in g[gfin].
-int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds) {
+// the final iterate in g[gfin].  In mixed precision the flux reads only the
+// FP32 shadows, so unless fp64_out is set (inspection) the last iterate's
+// FP64 copy is not written.
+int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds, bool fp64_out) {
     // the first pass goes to g[2] when inner iterations follow (they read it
     // as g0); the iterates alternate between g[0] and g[1]
     const int first = s->prm.n_inner > 0 ? 2 : 0;
     // mixed precision: the last pass also writes the FP32 shadow of g, the
     // first pass the FP32 shadow of the bounds
     const bool mixed = s->prm.precision == 1;
+    const bool skip64 = mixed && !fp64_out;
     Shadow sh{nullptr, nullptr, nullptr};
     if (mixed) {
         sh.qmm32 = s->qmm32;
@@ -411,10 +414,11 @@ int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds) {
     int cur = first;
     for (int k = 0; k < s->prm.n_inner; ++k) {
         const int nxt = (cur == 0) ? 1 : 0;
-        float4 *g32 = (mixed && k == s->prm.n_inner - 1) ? s->g32 : nullptr;
+        const bool last = k == s->prm.n_inner - 1;
+        float4 *g32 = (mixed && last) ? s->g32 : nullptr;
         Timer t(s, 1);
         HIPCHK(s, launch_gradk(s->stream, c, s->prm.grad_lds > 0 ? s->prm.grad_lds : kGradkLds,
-                               s->g[2], s->g[cur], s->g[nxt], g32));
+                               s->g[2], s->g[cur], (skip64 && last) ? nullptr : s->g[nxt], g32));
         t.done();
         cur = nxt;
     }
@@ -462,7 +466,7 @@ int enqueue_iteration(ql_solver *s, const DevCloud &c, const FlowParams &fp, int
     for (int rk = 1; rk <= 4; ++rk) {
         int st = QL_OK;
         // the first-order scheme needs no q-derivatives
-        if (fp.order == 2 && (st = run_gradients(s, c, fp.limiter != 0))) return st;
+        if (fp.order == 2 && (st = run_gradients(s, c, fp.limiter != 0, false))) return st;
         Timer t(s, 2);
         st = launch_stage(s, c, fp, rk, rk == 1 ? s->R : nullptr);
         if (st) return st;
@@ -955,7 +959,7 @@ int ql_evaluate(ql_solver *s) {
     const FlowParams fp = flow_params(s);
     st = reset_err(s);
     if (st) return st;
-    st = run_gradients(s, c, true);
+    st = run_gradients(s, c, true, true);
     if (st) return st;
     st = launch_stage(s, c, fp, 0, s->R);
     if (st) return st;
@@ -1070,7 +1074,7 @@ int ql_forces(ql_solver *s, double *cl, double *cd) {
 static int warm_eval(ql_solver *s, const DevCloud &c, const FlowParams &fp) {
     int st = prep_state(s);
     if (st) return st;
-    if ((st = run_gradients(s, c, fp.limiter != 0))) return st;
+    if ((st = run_gradients(s, c, fp.limiter != 0, false))) return st;
     if ((st = launch_stage(s, c, fp, 0, s->R))) return st;
     HIPCHK(s, launch_resnorm(s->stream, s->R, s->n, s->nchunk, s->chunk_beg, s->part, s->ncase,
                              s->chunk_ptr, s->inv_nupd, s->wctr, 2, s->wres));
@@ -1260,7 +1264,7 @@ int ql_autotune(ql_solver *s, const char *cache_path, int32_t *chosen) {
                           32 << 10};
     const ql_params saved = s->prm;
     double best_f = 1e30, best_g = 1e30, us = 0.0;
-    if ((st = reset_err(s)) || (st = prep_state(s)) || (st = run_gradients(s, c, fp.limiter != 0)))
+    if ((st = reset_err(s)) || (st = prep_state(s)) || (st = run_gradients(s, c, fp.limiter != 0, false)))
         goto done;
     for (int b : flux_c) {
         s->prm.flux_lds = b;
@@ -1273,7 +1277,7 @@ int ql_autotune(ql_solver *s, const char *cache_path, int32_t *chosen) {
     s->prm.flux_lds = saved.flux_lds;
     for (int b : grad_c) {
         s->prm.grad_lds = b;
-        if ((st = timed([&] { return run_gradients(s, c, fp.limiter != 0); }, 3, &us))) goto done;
+        if ((st = timed([&] { return run_gradients(s, c, fp.limiter != 0, false); }, 3, &us))) goto done;
         if (us < best_g) {
             best_g = us;
             bg = b;

@@ -226,6 +226,41 @@ def test_c2_full_size_evaluate(ql):
         assert np.all(err <= 10.0 * floor + 1e-14), (key, err, floor)
 
 
+def _sampled_iteration_check(c, U, Ugpu, prm, seed, count=48):
+    """One whole iteration (four stages) from U: the GPU state at sampled
+    points against the oracle on their dependency sub-clouds of depth
+    4 (n_inner + 2) + 1, which reproduce the whole-cloud iteration bit for
+    bit, within 10x the FMA-contraction noise floor."""
+    centres = sample_points(c, count, seed=seed)
+    depth = 4 * (oracle.params()["n_inner"] + 2) + 1
+    sub, members, where = dependency_subcloud(c, centres, depth)
+    ora, _ = oracle.Oracle(sub, oracle.params(**prm)).run(U[:, members], 1)
+    fma, _ = oracle.Oracle(sub, oracle.params(**prm),
+                           lib=oracle.load(oracle.FMA_LIB)).run(U[:, members], 1)
+    ref = ora[:, where]
+    floor = normwise_rel(fma[:, where], ref)
+    err = normwise_rel(Ugpu[:, centres], ref)
+    _say(f"  one iteration at {centres.size} samples (sub-clouds {sub.n} points): "
+         f"gpu {err.max():.2e}  floor {floor.max():.2e}")
+    assert np.all(err <= 10.0 * floor + 1e-15), (err, floor)
+
+
+def test_c2_sampled_iteration(ql):
+    """2.5M-point cloud (the benchmark's launch configuration), limiter on,
+    from a smooth state: one whole iteration on the GPU against the oracle on
+    dependency sub-clouds of the sampled points."""
+    _say("c2 sampled iteration")
+    c = cloud("c2")
+    prm = dict(limiter=1, mach=0.85, alpha_deg=1.0)
+    U = smooth_state(c, mach=0.85, alpha_deg=1.0)
+    s = ql.Solver(c, **prm)
+    s.set_state(U)
+    s.step(1)
+    U1 = s.fetch_state()
+    s.close()
+    _sampled_iteration_check(c, U, U1, prm, seed=17)
+
+
 @pytest.mark.skipif(not os.environ.get("QL_NACA40M"),
                     reason="the 40M-point cloud takes minutes to build; set QL_NACA40M to a "
                            ".npz path (the cloud is cached there) to run this check")
@@ -239,7 +274,8 @@ def test_c5_sampled_evaluate(ql):
     points and the longest neighbour lists) with the oracle evaluated on each
     sample's dependency sub-cloud (n_inner + 2 neighbour hops, which gives
     the whole-cloud values bit for bit), within 10x the FMA-contraction noise
-    floor as in the 2.5M check."""
+    floor as in the 2.5M check; and one whole iteration checked the same way
+    on depth-21 sub-clouds."""
     from cloudgen import naca_ocloud_cached
     _say("c5 sampled evaluate")
     c = naca_ocloud_cached(os.environ["QL_NACA40M"], 5000, 8000, jitter=0.1, seed=2108,
@@ -252,7 +288,11 @@ def test_c5_sampled_evaluate(ql):
     U = smooth_state(c, mach=0.85, alpha_deg=1.0)
     s.set_state(U)
     gpu = s.evaluate()
+    s.set_state(U)
+    s.step(1)
+    U1 = s.fetch_state()
     s.close()
+    _sampled_iteration_check(c, U, U1, prm, seed=19)
     centres = sample_points(c, 320, seed=5)
     sub, members, where = dependency_subcloud(c, centres, oracle.params()["n_inner"] + 2)
     _say(f"  {centres.size} samples, sub-clouds {sub.n} points")

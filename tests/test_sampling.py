@@ -35,3 +35,22 @@ def test_dependency_subcloud_matches_whole_cloud(oracle_lib, name, limiter, orde
     if depth > 1:
         part2 = oracle.Oracle(sub2, prm).evaluate(U[:, members2])
         assert np.any(part2["R"][:, where2] != full["R"][:, centres])
+
+
+def test_dependency_subcloud_one_iteration(oracle_lib):
+    """A whole pseudo-time iteration (four stages, each reaching n_inner + 2
+    hops) on sub-clouds of depth 4 (n_inner + 2) + 1 gives the whole-cloud
+    state at the sampled points bit for bit (400 x 300 jittered cloud,
+    limiter on)."""
+    from cloudgen import naca_ocloud
+    c = naca_ocloud(400, 300, jitter=0.1, seed=5)
+    flow = dict(mach=0.85, alpha_deg=1.0)
+    prm = oracle.params(limiter=1, **flow)
+    U = smooth_state(c, **flow)
+    full, _ = oracle.Oracle(c, prm).run(U, 1)
+    centres = sample_points(c, 12, seed=13)
+    depth = 4 * (prm["n_inner"] + 2) + 1
+    sub, members, where = dependency_subcloud(c, centres, depth)
+    assert sub.n < c.n
+    part, _ = oracle.Oracle(sub, prm).run(U[:, members], 1)
+    np.testing.assert_array_equal(part[:, where], full[:, centres])
