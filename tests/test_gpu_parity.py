@@ -3,7 +3,8 @@ identical seeded inputs.
 
 Tolerances: flags are integer work and must match bit for bit.  One
 evaluation of the stage operator matches q to 1e-13, the q-derivatives to
-1e-12, the bounds exactly and the residual to 5e-12 normwise per component
+1e-12, the bounds to 1e-15 (the library holds them as offsets from q and
+returns q plus offset) and the residual to 5e-12 normwise per component
 (each perturbation G(q~_i) - G(q~_0) is a difference of nearby values, which
 amplifies the few-ulp differences of its operands by 1/(h |grad G|/|G|),
 about 3e3 on these clouds); 100 iterations match to
