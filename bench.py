@@ -287,6 +287,8 @@ def main():
     ap.add_argument("--precision", choices=("both", "fp64", "mixed"), default="both")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="naca2.5m",
                     help="naca40m runs the throughput runs only (no studies, no CPU baseline)")
+    ap.add_argument("--reorder", choices=("hilbert", "rcm", "none"), default="hilbert",
+                    help="point order the library works in (results are the same bit for bit)")
     ap.add_argument("--cloud-cache", default="", metavar="NPZ",
                     help="keep the generated cloud in this file and reuse it when present")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -303,6 +305,8 @@ def main():
     from paper_2108_07031_amd import qlskum as ql
 
     wl = WORKLOADS[args.workload]
+    reorder = {"none": 0, "hilbert": 1, "rcm": 2}[args.reorder]
+    order_name = {"none": "caller order", "hilbert": "Hilbert order", "rcm": "RCM order"}[args.reorder]
     headline = args.workload == "naca2.5m"
     t0 = time.perf_counter()
     cloud = naca_ocloud_cached(args.cloud_cache, wl["ns"], wl["nr"], jitter=0.1, seed=2108,
@@ -315,7 +319,7 @@ def main():
 
     def timed_run(precision):
         t_up = time.perf_counter()
-        s = ql.Solver(cloud, stream=stream, precision=precision, **FLOW)
+        s = ql.Solver(cloud, stream=stream, precision=precision, reorder=reorder, **FLOW)
         log(f"[{PREC_NAME[precision]}] upload {time.perf_counter() - t_up:.1f} s")
         flags = s.flags()
         s.init_freestream()
@@ -377,7 +381,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"q-LSKUM, NACA 0012 O-cloud {wl['ns']}x{wl['nr']} "
-                        f"({cloud.n / 1e6:g}M pts), jitter 0.1 seed 2108, Hilbert order, M 0.85, "
+                        f"({cloud.n / 1e6:g}M pts), jitter 0.1 seed 2108, {order_name}, M 0.85, "
                         "alpha 1, Venkatakrishnan K 5, CFL 0.2, 3 inner iterations",
             "n_points": cloud.n,
             "nnz": cloud.nnz,

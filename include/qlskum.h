@@ -73,7 +73,8 @@ typedef struct {
     int32_t precision;/* 0 FP64 throughout; 1 mixed: reconstruction, limiter
                          and split fluxes in FP32, least-squares weights,
                          residual sums and the state update in FP64           */
-    int32_t reorder;  /* read at upload: 0 caller order, 1 Hilbert curve        */
+    int32_t reorder;  /* read at upload: 0 caller order, 1 Hilbert curve,
+                       * 2 reverse Cuthill-McKee on the neighbour graph      */
     int32_t flux_lds; /* tuning: bytes of LDS in which a flux workgroup stages
                          the records of its 64-point tile and halo (tiles that
                          do not fit read from memory; same results either

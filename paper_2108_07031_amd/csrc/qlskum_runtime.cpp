@@ -210,6 +210,83 @@ std::vector<int> hilbert_order(int n, const double *x, const double *y) {
     return perm;
 }
 
+// Reverse Cuthill-McKee order of the points lo..hi-1 (one case; indices
+// relative to lo) on the neighbour graph: breadth-first from a
+// pseudo-peripheral point (George and Liu: restart from the least-connected
+// point of the last level while the level count grows), each point's
+// unvisited neighbours taken by increasing neighbour count, ties by index;
+// every connected part in turn; the whole order reversed.
+std::vector<int> rcm_order(int lo, int hi, const int32_t *ptr, const int32_t *idx) {
+    const int n = hi - lo;
+    auto deg = [&](int p) { return ptr[lo + p + 1] - ptr[lo + p]; };
+    std::vector<int> order, level(n, -1), queue, nb;
+    order.reserve(n);
+    std::vector<char> done(n, 0);
+    // levels of a breadth-first search from r (over points not yet ordered);
+    // returns the depth and leaves the last level's least-connected point in far
+    auto bfs_depth = [&](int r, int &far) {
+        queue.assign(1, r);
+        level[r] = 0;
+        std::vector<int> seen(1, r);
+        int depth = 0;
+        far = r;
+        for (size_t h = 0; h < queue.size(); ++h) {
+            const int p = queue[h];
+            if (level[p] > depth) {
+                depth = level[p];
+                far = p;
+            } else if (level[p] == depth && deg(p) < deg(far)) {
+                far = p;
+            }
+            for (int k = ptr[lo + p]; k < ptr[lo + p + 1]; ++k) {
+                const int i = idx[k] - lo;
+                if (level[i] < 0 && !done[i]) {
+                    level[i] = level[p] + 1;
+                    queue.push_back(i);
+                    seen.push_back(i);
+                }
+            }
+        }
+        for (int p : seen) level[p] = -1;
+        return depth;
+    };
+    std::vector<int> by_deg(n);
+    std::iota(by_deg.begin(), by_deg.end(), 0);
+    std::stable_sort(by_deg.begin(), by_deg.end(), [&](int a, int b) { return deg(a) < deg(b); });
+    for (int start : by_deg) {
+        if (done[start]) continue;
+        int r = start, far = start, depth = bfs_depth(r, far);
+        for (int it = 0; it < 8; ++it) {  // pseudo-peripheral start
+            int far2 = far;
+            const int d2 = bfs_depth(far, far2);
+            if (d2 <= depth) break;
+            r = far;
+            depth = d2;
+            far = far2;
+        }
+        queue.assign(1, r);
+        done[r] = 1;
+        for (size_t h = 0; h < queue.size(); ++h) {
+            const int p = queue[h];
+            order.push_back(p);
+            nb.clear();
+            for (int k = ptr[lo + p]; k < ptr[lo + p + 1]; ++k) {
+                const int i = idx[k] - lo;
+                if (!done[i]) {
+                    done[i] = 1;
+                    nb.push_back(i);
+                }
+            }
+            std::stable_sort(nb.begin(), nb.end(), [&](int a, int b) {
+                return deg(a) < deg(b) || (deg(a) == deg(b) && a < b);
+            });
+            queue.insert(queue.end(), nb.begin(), nb.end());
+        }
+    }
+    std::reverse(order.begin(), order.end());
+    return order;
+}
+
 // Tiles of T consecutive points: the sorted list of each tile's halo
 // (neighbours outside the tile) and every entry's slot in the tile's LDS
 // image (own point j -> j, halo point h -> T + h).  Returns the largest image
@@ -298,7 +375,7 @@ int check_params(ql_solver *s, const ql_params *p) {
     if (p->limiter && !(p->venkat_k > 0.0)) return fail(s, QL_EINVAL, "venkat_k must be > 0");
     if (p->precision != 0 && p->precision != 1)
         return fail(s, QL_EINVAL, "precision must be 0 (FP64) or 1 (mixed)");
-    if (p->reorder != 0 && p->reorder != 1) return fail(s, QL_EINVAL, "reorder must be 0 or 1");
+    if (p->reorder < 0 || p->reorder > 2) return fail(s, QL_EINVAL, "reorder must be 0, 1 or 2");
     if (p->flux_lds < 0 || p->flux_lds > 160 * 1024)
         return fail(s, QL_EINVAL, "flux_lds must lie in [0, 163840] bytes");
     if (p->grad_lds < 0 || p->grad_lds > 160 * 1024)
@@ -670,6 +747,9 @@ static int upload_impl(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int
         const int lo = (int)case_ptr[c], hi = (int)case_ptr[c + 1];
         if (s->prm.reorder == 1) {
             const std::vector<int> o = hilbert_order(hi - lo, x + lo, y + lo);
+            for (int j = 0; j < hi - lo; ++j) perm[lo + j] = lo + o[j];
+        } else if (s->prm.reorder == 2) {
+            const std::vector<int> o = rcm_order(lo, hi, nbr_ptr, nbr_idx);
             for (int j = 0; j < hi - lo; ++j) perm[lo + j] = lo + o[j];
         } else {
             for (int j = lo; j < hi; ++j) perm[j] = j;
