@@ -7,8 +7,10 @@ gives R = 0 exactly (identical reconstructed states give identical FP32
 fluxes); one evaluation's residual lies within 2e-3 normwise of the FP64
 oracle (each perturbation G(q~_i) - G(q~_0) is a difference of nearby
 values, so FP32 rounding of the two states, ~6e-8 relative, is amplified by
-1/(h |grad G|/|G|), up to ~3e3 on these clouds); converged lift and drag
-within 1e-4 of the FP64 solution.
+1/(h |grad G|/|G|), up to ~3e3 on these clouds); the residual levels off
+about five and a half decades below its first value (the same rounding,
+now in the converged state), where lift and drag are within 1e-4 of the
+FP64 solution.
 """
 import numpy as np
 import pytest
@@ -66,19 +68,28 @@ def test_mixed_evaluate_close_to_oracle(ql, limiter):
 
 
 def test_mixed_converged_forces(ql):
-    """9,600-point cloud, M 0.63, alpha 2: converged lift and drag of the
-    mixed path within 1e-4 of the FP64 path."""
+    """9,600-point cloud, M 0.63, alpha 2, from the freestream: the FP64 path
+    brings the density residual six decades below its first value within
+    60,000 iterations (measured: 45,696); the mixed path levels off near
+    5.5e-6 of it -- the rounding floor of its FP32 flux body -- and must get
+    below 1e-5; their lift and drag then agree within 1e-4 and the density
+    within 1e-3."""
     _say("mixed converged forces")
     c = cloud("c1")
     out = {}
     for prec in (0, 1):
         s = ql.Solver(c, precision=prec)
         s.init_freestream()
-        h = s.step(30000)
-        out[prec] = (s.forces(), s.fetch_state(), h)
-        _say(f"  precision {prec}: residual drop {h[-1, 0] / h[0, 0]:.2e}, cl, cd {out[prec][0]}")
+        h = s.step(1)
+        iters, res = s.batch_run(1e-6, 60000, check_every=1000, ref=h[:1, 0])
+        drop = res[0, 0] / h[0, 0]
+        out[prec] = (s.forces(), s.fetch_state(), int(iters[0]), drop)
+        _say(f"  precision {prec}: {int(iters[0])} iterations, density residual drop {drop:.2e}, "
+             f"cl, cd {out[prec][0]}")
         s.close()
-    (cl0, cd0), U0, _ = out[0]
-    (cl1, cd1), U1, _ = out[1]
+    (cl0, cd0), U0, it0, drop0 = out[0]
+    (cl1, cd1), U1, it1, drop1 = out[1]
+    assert it0 < 60000 and drop0 <= 1e-6, (it0, drop0)
+    assert drop1 <= 1e-5, drop1
     assert abs(cl1 - cl0) <= 1e-4 and abs(cd1 - cd0) <= 1e-4
     assert normwise_rel(U1[:1], U0[:1]).max() <= 1e-3

@@ -121,6 +121,47 @@ def test_freestream_preservation(ql):
         s.close()
 
 
+def test_mirror_symmetry_zero_incidence(ql):
+    """Mirror-exact 160 x 60 cloud (the lower half is the upper half
+    reflected, with reflected normals and neighbour lists), M 0.63, zero
+    incidence: after 2000 iterations |C_l| <= 1e-10 and the density at each
+    point equals that at its mirror image to 1e-10."""
+    _say("mirror symmetry")
+    c = cloud("c1")
+    ns = c.meta["ns"]
+    s = ql.Solver(c, mach=0.63, alpha_deg=0.0)
+    s.init_freestream()
+    s.step(2000, want_history=False)
+    U = s.fetch_state()
+    cl, _ = s.forces()
+    s.close()
+    p = np.arange(c.n)
+    mirror = (p // ns) * ns + (ns - p % ns) % ns
+    np.testing.assert_array_equal(c.x[mirror], c.x)
+    np.testing.assert_array_equal(c.y[mirror], -c.y)
+    _say(f"  cl {cl:.3e}, max density asymmetry {np.abs(U[0] - U[0, mirror]).max():.3e}")
+    assert abs(cl) <= 1e-10
+    assert np.abs(U[0] - U[0, mirror]).max() <= 1e-10
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_wall_tangency(ql, precision):
+    """After every iteration (the wall projection follows every stage) the
+    wall momentum is tangent: |m . n| <= 1e-14 |m| at every wall point."""
+    _say(f"wall tangency precision={precision}")
+    c = cloud("jitter")
+    s = ql.Solver(c, limiter=1, mach=0.85, alpha_deg=1.0, precision=precision)
+    s.init_freestream()
+    wall = c.kind == 1
+    for _ in range(5):
+        s.step(3, want_history=False)
+        U = s.fetch_state()
+        m1, m2 = U[1, wall], U[2, wall]
+        mn = np.abs(m1 * c.nx[wall] + m2 * c.ny[wall])
+        assert np.all(mn <= 1e-14 * np.hypot(m1, m2) + 1e-300), mn.max()
+    s.close()
+
+
 def test_checkpoint_restart_bitwise(ql):
     _say("checkpoint")
     c = cloud("small")
