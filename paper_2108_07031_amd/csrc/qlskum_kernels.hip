@@ -884,25 +884,34 @@ __device__ __forceinline__ bool flux_entry(uint8_t f, double dx, double dy, doub
     Prim si, s0;
     bool ok = q_to_prim<POW>(qti, fp, si);
     ok &= q_to_prim<POW>(qt0, fp, s0);
-    if ((DIRS & 1) && (f & (kSPlus | kSMinus))) {
+    // both directions without branches (an entry outside a direction's
+    // stencils gets weight 0), so that the four split-flux evaluations are
+    // independent straight-line work the scheduler can interleave
+    double Gs[2][4], Gn[2][4];
+    double ws = 0.0, wn = 0.0;
+    if (DIRS & 1) {
         const bool plus = (f & kSPlus) != 0;
         const double sg = plus ? 1.0 : -1.0;
-        const double wt = fma(ds, plus ? w[0] : w[2], -(dn * (plus ? w[1] : w[3])));
-        double Gi[4], G0[4];
-        split_flux(si, tx, ty, sg, Gi);
-        split_flux(s0, tx, ty, sg, G0);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) R[r] = fma(wt, Gi[r] - G0[r], R[r]);
+        ws = (f & (kSPlus | kSMinus)) ? fma(ds, plus ? w[0] : w[2], -(dn * (plus ? w[1] : w[3])))
+                                      : 0.0;
+        split_flux(si, tx, ty, sg, Gs[0]);
+        split_flux(s0, tx, ty, sg, Gs[1]);
     }
-    if ((DIRS & 2) && (f & (kNPlus | kNMinus))) {
+    if (DIRS & 2) {
         const bool plus = (f & kNPlus) != 0;
         const double sg = plus ? 1.0 : -1.0;
-        const double wt = fma(dn, plus ? w[4] : w[6], -(ds * (plus ? w[5] : w[7])));
-        double Gi[4], G0[4];
-        split_flux(si, N.x, N.y, sg, Gi);
-        split_flux(s0, N.x, N.y, sg, G0);
+        wn = (f & (kNPlus | kNMinus)) ? fma(dn, plus ? w[4] : w[6], -(ds * (plus ? w[5] : w[7])))
+                                      : 0.0;
+        split_flux(si, N.x, N.y, sg, Gn[0]);
+        split_flux(s0, N.x, N.y, sg, Gn[1]);
+    }
+    if (DIRS & 1) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) R[r] = fma(wt, Gi[r] - G0[r], R[r]);
+        for (int r = 0; r < 4; ++r) R[r] = fma(ws, Gs[0][r] - Gs[1][r], R[r]);
+    }
+    if (DIRS & 2) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) R[r] = fma(wn, Gn[0][r] - Gn[1][r], R[r]);
     }
     return ok;
 }
@@ -968,7 +977,10 @@ __device__ __forceinline__ void rk_update(const DevCloud &cl, const FlowParams &
 int num_flux_tiles(int n) { return (n + kFluxTile - 1) / kFluxTile; }
 
 template <bool LIMITER, int POW, bool FIRST, int DIRS>
-__global__ void __launch_bounds__(kBlock) k_flux(DevCloud cl, FlowParams fp, int stage, int cap,
+// Held to 3 waves per SIMD (at most 168 VGPRs), which the straight-line
+// two-direction body of flux_entry would otherwise exceed.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+k_flux(DevCloud cl, FlowParams fp, int stage, int cap,
                                                  const double *__restrict__ Rin,
                                                  const double2 *__restrict__ q,
                                                  const double2 *__restrict__ g,
