@@ -1271,33 +1271,30 @@ __device__ __forceinline__ bool flux_entry_f(uint8_t f, double dx, double dy, do
     PrimF si, s0;
     bool ok = q_to_prim_f<POW>(qti, gm1inv, si);
     ok &= q_to_prim_f<POW>(qt0, gm1inv, s0);
-    if (f & (kSPlus | kSMinus)) {
-        const bool plus = (f & kSPlus) != 0;
-        const float sg = plus ? 1.0f : -1.0f;
-        const double wt = fma(ds, plus ? w[0] : w[2], -(dn * (plus ? w[1] : w[3])));
-        float Gi[4], G0[4];
-        split_flux_f(si, (float)tx, (float)ty, sg, Gi);
-        split_flux_f(s0, (float)tx, (float)ty, sg, G0);
+    // both directions as straight-line code, as in flux_entry
+    float Gs[2][4], Gn[2][4];
+    const bool sp = (f & kSPlus) != 0, np_ = (f & kNPlus) != 0;
+    const double ws = (f & (kSPlus | kSMinus))
+                          ? fma(ds, sp ? w[0] : w[2], -(dn * (sp ? w[1] : w[3]))) : 0.0;
+    const double wn = (f & (kNPlus | kNMinus))
+                          ? fma(dn, np_ ? w[4] : w[6], -(ds * (np_ ? w[5] : w[7]))) : 0.0;
+    split_flux_f(si, (float)tx, (float)ty, sp ? 1.0f : -1.0f, Gs[0]);
+    split_flux_f(s0, (float)tx, (float)ty, sp ? 1.0f : -1.0f, Gs[1]);
+    split_flux_f(si, (float)N.x, (float)N.y, np_ ? 1.0f : -1.0f, Gn[0]);
+    split_flux_f(s0, (float)N.x, (float)N.y, np_ ? 1.0f : -1.0f, Gn[1]);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) R[r] = fma(wt, (double)(Gi[r] - G0[r]), R[r]);
-    }
-    if (f & (kNPlus | kNMinus)) {
-        const bool plus = (f & kNPlus) != 0;
-        const float sg = plus ? 1.0f : -1.0f;
-        const double wt = fma(dn, plus ? w[4] : w[6], -(ds * (plus ? w[5] : w[7])));
-        float Gi[4], G0[4];
-        split_flux_f(si, (float)N.x, (float)N.y, sg, Gi);
-        split_flux_f(s0, (float)N.x, (float)N.y, sg, G0);
+    for (int r = 0; r < 4; ++r) R[r] = fma(ws, (double)(Gs[0][r] - Gs[1][r]), R[r]);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) R[r] = fma(wt, (double)(Gi[r] - G0[r]), R[r]);
-    }
+    for (int r = 0; r < 4; ++r) R[r] = fma(wn, (double)(Gn[0][r] - Gn[1][r]), R[r]);
     return ok;
 }
 
 }  // namespace
 
 template <bool LIMITER, int POW, bool FIRST>
-__global__ void __launch_bounds__(kBlock) k_flux_mixed(
+// held to 4 waves per SIMD (at most 128 VGPRs), as k_flux is to 3
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+k_flux_mixed(
     DevCloud cl, FlowParams fp, int stage, int cap, const double2 *__restrict__ q,
     const float4 *__restrict__ q32, const float4 *__restrict__ g32,
     const float4 *__restrict__ qmm32, double *__restrict__ U, double *__restrict__ Un,
