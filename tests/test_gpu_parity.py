@@ -349,6 +349,38 @@ def test_c5_sampled_evaluate(ql):
         assert np.all(err <= 10.0 * floor + 1e-14), (key, err, floor)
 
 
+@pytest.mark.parametrize("limiter", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_general_gamma_parity(ql, limiter, precision):
+    """gamma = 1.3, which takes the general q~ -> primitive conversion (a
+    logarithm and an exponential) instead of the gamma = 1.4 form with
+    (1/sqrt(beta))^5: one evaluation to the evaluation bounds (mixed: 2e-3)
+    and, in FP64, 30 iterations to 1e-11 against the oracle."""
+    _say(f"gamma 1.3 limiter={limiter} precision={precision}")
+    c = cloud("jitter")
+    prm = dict(gamma=1.3, limiter=limiter, mach=0.85 if limiter else 0.63,
+               alpha_deg=1.0 if limiter else 2.0)
+    o = oracle.Oracle(c, oracle.params(**prm))
+    s = ql.Solver(c, precision=precision, **prm)
+    U = smooth_state(c, mach=prm["mach"], alpha_deg=prm["alpha_deg"], gamma=1.3)
+    s.set_state(U)
+    gpu = s.evaluate()
+    ora = o.evaluate(U)
+    tol = dict(q=1e-13, g=1e-12, R=5e-12, dt=1e-14) if precision == 0 else dict(R=2e-3)
+    for key, t in tol.items():
+        err = normwise_rel(gpu[key], ora[key])
+        assert np.all(err <= t), (key, err)
+    if precision == 0:
+        s.init_freestream()
+        U0 = s.fetch_state()
+        s.step(30)
+        U1, _ = o.run(U0, 30)
+        err = normwise_rel(s.fetch_state(), U1)
+        _say(f"  30 iterations: {err}")
+        assert np.all(err <= 1e-11), err
+    s.close()
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_first_order_parity(ql, precision):
     """First-order mode (order = 1, split fluxes of q itself): one evaluation
