@@ -349,6 +349,35 @@ def test_c5_sampled_evaluate(ql):
         assert np.all(err <= 10.0 * floor + 1e-14), (key, err, floor)
 
 
+@pytest.mark.parametrize("n_inner", [0, 1, 5])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_inner_iteration_counts(ql, n_inner, precision):
+    """Other inner-iteration counts than 3 (0: the first pass alone, which
+    then also writes the FP32 shadow of g for the mixed path): one
+    evaluation against the oracle with the same count, limiter on, to the
+    evaluation bounds (mixed: 2e-3), and 10 iterations in FP64 to 1e-11."""
+    _say(f"n_inner={n_inner} precision={precision}")
+    c = cloud("jitter")
+    prm = dict(n_inner=n_inner, limiter=1, mach=0.85, alpha_deg=1.0)
+    o = oracle.Oracle(c, oracle.params(**prm))
+    s = ql.Solver(c, precision=precision, **prm)
+    U = smooth_state(c, mach=0.85, alpha_deg=1.0)
+    s.set_state(U)
+    gpu = s.evaluate()
+    ora = o.evaluate(U)
+    tol = dict(q=1e-13, g=1e-12, R=5e-12) if precision == 0 else dict(g=1e-12, R=2e-3)
+    for key, t in tol.items():
+        err = normwise_rel(gpu[key], ora[key])
+        assert np.all(err <= t), (key, err)
+    if precision == 0:
+        s.init_freestream()
+        U0 = s.fetch_state()
+        s.step(10)
+        U1, _ = o.run(U0, 10)
+        assert np.all(normwise_rel(s.fetch_state(), U1) <= 1e-11)
+    s.close()
+
+
 @pytest.mark.parametrize("limiter", [0, 1])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_general_gamma_parity(ql, limiter, precision):
