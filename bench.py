@@ -200,12 +200,16 @@ def warm_study():
     t0 = time.perf_counter()
     it_train, _ = s.batch_run(W["drop"], W["max_iter"], check_every=500)
     t_conv = time.perf_counter() - t0
+    # train on the cases that reached the drop (a failed case is retired
+    # with its status and keeps an unusable state)
+    ok_case = (s.batch_status() == ql.QL_OK) & (np.asarray(it_train) < W["max_iter"])
     U = s.fetch_state()
     d = s.wall_distance()
     s.close()
     F = np.concatenate([warm_features(cl, d[offs[i]:offs[i + 1]], c["mach"], c["alpha"],
                                       c["tau"]) for i, (cl, c) in enumerate(zip(clouds, train))])
-    keep = np.concatenate([cl.kind for cl in clouds]) != 2
+    keep = (np.concatenate([cl.kind for cl in clouds]) != 2) & np.repeat(
+        ok_case, [cl.n for cl in clouds])
     F, P = F[keep], _prims(U)[keep]
     fm, fs = F.mean(axis=0), F.std(axis=0) + 1e-12
     pm, ps = P.mean(axis=0), P.std(axis=0) + 1e-12
@@ -238,6 +242,8 @@ def warm_study():
         t0 = time.perf_counter()
         sc.init_freestream()
         ic, rc_last = sc.batch_run(W["drop"], W["max_iter"], check_every=100)
+        if sc.batch_status()[0] != ql.QL_OK:
+            raise RuntimeError(f"cold run failed at M {c['mach']:.3f}, alpha {c['alpha']:.2f}")
         t_cold = time.perf_counter() - t0
         dw = sc.wall_distance()
         sc.close()
@@ -248,6 +254,8 @@ def warm_study():
         t0 = time.perf_counter()
         rcold, rwarm, used = sw.warm_start(m, Xc, np.concatenate([pm, ps]), W["floor"])
         iw, _ = sw.batch_run(W["drop"], W["max_iter"], check_every=100, ref=rcold[:, 0])
+        if sw.batch_status()[0] != ql.QL_OK:
+            raise RuntimeError(f"warm run failed at M {c['mach']:.3f}, alpha {c['alpha']:.2f}")
         t_warm = time.perf_counter() - t0
         sw.close()
         rows.append(dict(iters_cold=int(ic[0]), iters_warm=int(iw[0]), t_cold=t_cold,
@@ -262,7 +270,7 @@ def warm_study():
         "cases_train": W["n_train"], "cases_test": W["n_test"],
         "points_per_case": W["ns"] * W["nr"],
         "drop": W["drop"], "max_iter": W["max_iter"],
-        "train_converged": int(np.sum(np.asarray(it_train) < W["max_iter"])),
+        "train_converged": int(np.sum(ok_case)),
         "train_solve_s": t_conv, "train_net_s": t_train, "train_loss": loss,
         "network": "6-128x4-4 tanh, bf16 MFMA, FP32 accumulate, Adam",
         "iters_cold": [r["iters_cold"] for r in rows],

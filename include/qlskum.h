@@ -210,10 +210,20 @@ int ql_batch_info(const ql_solver *s, int32_t *ncase);
  * parameter or buffer changes) and replays it.  iters_out[c] (nullable)
  * receives the iteration at which case c reached the drop (or the
  * iterations run), res_out[c][4] (nullable) its last norms.
- * Errors: as ql_step; QL_EINVAL (drop <= 0, max_iter < 0, check_every < 1,
- * a reference <= 0 or not finite). */
+ * A case whose state fails (positivity lost, or a non-finite value) is
+ * retired with that status while the other cases go on; ql_batch_status
+ * reports it.  Its state is left as it was when the failure was found (not
+ * usable: set a new state before stepping again).
+ * Errors: as ql_step for failures that name no case; QL_EINVAL (drop <= 0,
+ * max_iter < 0, check_every < 1, a reference <= 0 or not finite). */
 int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_every, int32_t graph,
                  const double *ref_res, int32_t *iters_out, double *res_out);
+
+/* Per-case outcome of the last ql_batch_run: status[c] = QL_OK (reached the
+ * drop or ran max_iter), QL_EPOSITIVITY or QL_ENONFINITE (case c failed and
+ * was retired).  status holds ncase entries (ql_batch_info); all QL_OK
+ * before any run.  Errors: QL_EINVAL (NULL), QL_ESTATE (no cloud). */
+int ql_batch_status(const ql_solver *s, int32_t *status);
 
 /* Lift and drag of every case (as ql_forces), cl[ncase], cd[ncase]. */
 int ql_batch_forces(ql_solver *s, double *cl, double *cd);

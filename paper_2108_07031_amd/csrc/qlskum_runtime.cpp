@@ -96,6 +96,7 @@ struct ql_solver {
     int err_init[2] = {INT_MAX, 0};  // source of the error-word reset copies
     int qcur = 0, gfin = 0;
     std::vector<double> last_res;  // [ncase][4]
+    std::vector<int32_t> case_status;  // per case, of the last ql_batch_run
     std::vector<double> uinf_host;  // [ncase][4], source of the s->uinf copy
 
     // one pseudo-time iteration captured as a graph (batched runs)
@@ -392,11 +393,8 @@ int reset_err(ql_solver *s) {
     return QL_OK;
 }
 
-// Synchronise and turn the device error word into a status.
-int sync_and_check(ql_solver *s, const char *what) {
-    int e[2];
-    HIPCHK(s, hipMemcpyAsync(e, s->errw, sizeof e, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(s, hipStreamSynchronize(s->stream));
+// Status of a device error word (library-order point e[0], code e[1]).
+static int err_status(ql_solver *s, const int e[2], const char *what) {
     if (e[1] == kErrNone) return QL_OK;
     const int up = (e[0] >= 0 && e[0] < s->n) ? s->perm[e[0]] : -1;
     switch (e[1]) {
@@ -409,6 +407,27 @@ int sync_and_check(ql_solver *s, const char *what) {
                     "%s: positivity lost (non-positive density/pressure or q4 >= 0) at point %d",
                     what, up);
     }
+}
+
+// Synchronise and read the device error word.
+static int read_err(ql_solver *s, int e[2]) {
+    HIPCHK(s, hipMemcpyAsync(e, s->errw, 2 * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return QL_OK;
+}
+
+// Synchronise and turn the device error word into a status.
+int sync_and_check(ql_solver *s, const char *what) {
+    int e[2];
+    int st = read_err(s, e);
+    if (st) return st;
+    return err_status(s, e, what);
+}
+
+// The case holding library-order point p (cases keep their point ranges).
+static int case_of_point(const ql_solver *s, int p) {
+    const auto it = std::upper_bound(s->case_lo.begin(), s->case_lo.end(), p);
+    return (int)(it - s->case_lo.begin()) - 1;
 }
 
 hipEvent_t take_event(ql_solver *s) {
@@ -810,6 +829,7 @@ static int upload_impl(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int
     if (mach) s->case_mach.assign(mach, mach + ncase);
     if (alpha) s->case_alpha.assign(alpha, alpha + ncase);
     s->last_res.assign((size_t)4 * ncase, 0.0);
+    s->case_status.assign(ncase, QL_OK);
     s->nw = (int)hwall.size();
     s->nchunk = nchunk;
     HIPCHK(s, dalloc(&s->xy, n)); HIPCHK(s, dalloc(&s->nrm, n)); HIPCHK(s, dalloc(&s->kind, n));
@@ -1408,6 +1428,14 @@ int ql_batch_info(const ql_solver *s, int32_t *ncase) {
     return QL_OK;
 }
 
+int ql_batch_status(const ql_solver *s, int32_t *status) {
+    if (!s || !status) return QL_EINVAL;
+    if (!s->has_cloud) return QL_ESTATE;
+    for (int c = 0; c < s->ncase; ++c)
+        status[c] = (c < (int)s->case_status.size()) ? s->case_status[c] : QL_OK;
+    return QL_OK;
+}
+
 int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_every, int32_t graph,
                  const double *ref_res, int32_t *iters_out, double *res_out) {
     int st = ensure_ready(s, true);
@@ -1426,6 +1454,7 @@ int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_ever
     std::vector<double> ref(nc, -1.0), last((size_t)4 * nc, 0.0);
     if (ref_res) ref.assign(ref_res, ref_res + nc);
     std::vector<int> iters(nc, 0);
+    std::vector<int32_t> status(nc, QL_OK);
     HIPCHK(s, hipMemcpyAsync(s->case_active, active.data(), nc, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemcpyAsync(s->tile_active, tile.data(), ntile, hipMemcpyHostToDevice, s->stream));
     if ((st = reset_err(s))) return st;
@@ -1445,9 +1474,25 @@ int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_ever
         }
         HIPCHK(s, hipMemcpyAsync(hist.data(), s->reshist, sizeof(double) * k * nc * 4,
                                  hipMemcpyDeviceToHost, s->stream));
-        if ((st = sync_and_check(s, "batch_run"))) return st;
+        int e[2];
+        if ((st = read_err(s, e))) return st;
         harvest_timing(s);
         bool changed = false;
+        if (e[1] != kErrNone) {
+            // a case whose state failed (positivity or a non-finite value)
+            // retires with that status; the others go on
+            const int fc = (e[0] >= 0 && e[0] < s->n) ? case_of_point(s, e[0]) : -1;
+            if ((e[1] != kErrPositivity && e[1] != kErrNonFinite) || fc < 0)
+                return err_status(s, e, "batch_run");
+            if (active[fc]) {
+                status[fc] = (e[1] == kErrPositivity) ? QL_EPOSITIVITY : QL_ENONFINITE;
+                iters[fc] += k;
+                active[fc] = 0;
+                --nactive;
+                changed = true;
+            }
+            if ((st = reset_err(s))) return st;
+        }
         for (int cs = 0; cs < nc; ++cs) {
             if (!active[cs]) continue;
             for (int r = 0; r < k; ++r) {
@@ -1491,8 +1536,18 @@ int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_ever
     HIPCHK(s, hipMemcpyAsync(s->case_active, active.data(), nc, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemcpyAsync(s->tile_active, tile.data(), ntile, hipMemcpyHostToDevice, s->stream));
     if ((st = prep_state(s))) return st;
-    if ((st = sync_and_check(s, "batch_run"))) return st;
+    {
+        // a failed case's state may still fail here; only failed cases can
+        int e[2];
+        if ((st = read_err(s, e))) return st;
+        if (e[1] != kErrNone) {
+            const int fc = (e[0] >= 0 && e[0] < s->n) ? case_of_point(s, e[0]) : -1;
+            if (fc < 0 || status[fc] == QL_OK) return err_status(s, e, "batch_run");
+            if ((st = reset_err(s))) return st;
+        }
+    }
     s->has_eval = false;
+    s->case_status = status;
     s->last_res = last;
     s->has_res = done > 0;
     if (iters_out) std::copy(iters.begin(), iters.end(), iters_out);

@@ -29,7 +29,8 @@ EXPORTS = ("ql_default_params", "ql_create", "ql_destroy", "ql_upload_cloud", "q
            "ql_init_freestream", "ql_set_state", "ql_step", "ql_residual_norm",
            "ql_fetch_state", "ql_forces", "ql_last_error", "ql_evaluate", "ql_debug_fetch",
            "ql_debug_flags", "ql_cloud_size", "ql_set_timing", "ql_kernel_time",
-           "ql_batch_upload", "ql_batch_info", "ql_batch_run", "ql_batch_forces",
+           "ql_batch_upload", "ql_batch_info", "ql_batch_run", "ql_batch_status",
+           "ql_batch_forces",
            "ql_flux_tiles", "ql_mlp_create", "ql_mlp_destroy", "ql_mlp_last_error",
            "ql_mlp_num_params", "ql_mlp_set_weights", "ql_mlp_get_weights", "ql_mlp_forward",
            "ql_mlp_gradient", "ql_mlp_train_step", "ql_mlp_sync", "ql_wall_distance",
@@ -95,6 +96,7 @@ def _load():
     lib.ql_wall_distance.argtypes = [vp, vp]
     lib.ql_warm_start.argtypes = [vp, vp, vp, vp, d, vp, vp, vp]
     lib.ql_autotune.argtypes = [vp, C.c_char_p, vp]
+    lib.ql_batch_status.argtypes = [vp, vp]
     for name in EXPORTS:
         if name not in ("ql_default_params", "ql_last_error", "ql_mlp_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -221,6 +223,14 @@ def ql_batch_run(s, drop, max_iter, check_every=100, graph=True, ref=None):
                                keep.ctypes.data if keep is not None else None,
                                iters.ctypes.data, res.ctypes.data))
     return iters, res
+
+
+def ql_batch_status(s):
+    """Per-case status of the last ql_batch_run (QL_OK, or the failure code
+    of a case that was retired)."""
+    out = np.zeros(ql_batch_info(s), np.int32)
+    _check(s, lib.ql_batch_status(s, out.ctypes.data))
+    return out
 
 
 def ql_autotune(s, cache_path=None):
@@ -499,6 +509,9 @@ class Solver:
 
     def batch_run(self, drop, max_iter, check_every=100, graph=True, ref=None):
         return ql_batch_run(self.h, drop, max_iter, check_every, graph, ref)
+
+    def batch_status(self):
+        return ql_batch_status(self.h)
 
     def wall_distance(self):
         return ql_wall_distance(self.h)

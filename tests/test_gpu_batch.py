@@ -99,3 +99,60 @@ def test_retirement_matches_solo(ql, clouds):
         assert iters[i] == k, (i, iters[i], k)
         U, _ = _solo(ql, cl, case, k, limiter=1)
         np.testing.assert_array_equal(Ub[:, offs[i]:offs[i + 1]], U)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_failed_case_retires_alone(ql, clouds, graph):
+    """Three cases without the limiter at conditions that run stably (M 0.63,
+    0.5 and 0.4); in the middle one a point's pressure is set to 1e-6, so
+    the reconstruction next to it gives q~4 >= 0 and the case fails.  It is
+    retired with its status within the first check window while the other
+    two run on; their states equal those of the same batch without the
+    failure bit for bit, and the solver runs on once every case has a valid
+    state again."""
+    _say(f"failed case graph={graph}")
+    prm = dict(limiter=0)
+    cl = [clouds[0], clouds[1], clouds[0]]
+    mach, alpha = [0.63, 0.5, 0.4], [2.0, -1.5, 0.0]
+
+    def batch(U=None, n=200):
+        s = ql.Solver(**prm)
+        offs = s.upload_batch(cl, mach, alpha)
+        if U is None:
+            s.init_freestream()
+        else:
+            s.set_state(U)
+        iters, _ = s.batch_run(1e-300, n, check_every=50, graph=graph)
+        return s, offs, iters
+
+    ref, offs, _ = batch()
+    assert list(ref.batch_status()) == [ql.QL_OK] * 3
+    ref.close()
+    ref, _, _ = batch(n=0)
+    U0 = ref.fetch_state()
+    ref.close()
+    ref, _, _ = batch(U0)
+    Uref = ref.fetch_state()
+    ref.close()
+    bad = U0.copy()
+    c1 = cl[1]
+    lp = (c1.meta["nr"] // 2) * c1.meta["ns"] + 7  # an interior point of case 1
+    assert c1.kind[lp] == 0
+    p0 = int(offs[1]) + lp
+    rho, m1, m2 = bad[0, p0], bad[1, p0], bad[2, p0]
+    bad[3, p0] = 1e-6 / 0.4 + 0.5 * (m1 * m1 + m2 * m2) / rho
+    s, _, iters = batch(bad)
+    status = s.batch_status()
+    _say(f"  status {status}, iterations {iters}")
+    assert status[0] == ql.QL_OK and status[2] == ql.QL_OK
+    assert status[1] in (ql.QL_EPOSITIVITY, ql.QL_ENONFINITE)
+    assert iters[0] == 200 and iters[2] == 200 and iters[1] <= 50
+    U = s.fetch_state()
+    for k in (0, 2):
+        lo, hi = int(offs[k]), int(offs[k + 1])
+        np.testing.assert_array_equal(U[:, lo:hi], Uref[:, lo:hi])
+    # every case valid again: the solver runs on, all statuses clear
+    s.set_state(U0)
+    s.batch_run(1e-300, 20, check_every=10, graph=graph)
+    assert list(s.batch_status()) == [ql.QL_OK] * 3
+    s.close()
