@@ -84,7 +84,8 @@ hipError_t launch_prep(hipStream_t st, const DevCloud &c, const FlowParams &fp, 
 // q-derivatives (tiled like the flux sweep; lds_budget as there): first
 // pass with the limiter bounds (qmm: qmax - q and qmin - q per point), and
 // one inner iteration from the first pass g0 and the previous iterate gprev.
-// gnext may be null when only the FP32 shadow (g32) is wanted.
+// gnext may be null when only the FP32 shadow (g32) is wanted, and qmm when
+// only the bounds' FP32 shadow (sh.qmm32) is.
 hipError_t launch_grad0(hipStream_t st, const DevCloud &c, int lds_budget, const double2 *q,
                         double2 *g, double2 *qmm, int want_bounds, Shadow sh);
 hipError_t launch_gradk(hipStream_t st, const DevCloud &c, int lds_budget, const double2 *g0,

@@ -445,7 +445,10 @@ __device__ __forceinline__ int slot_point(const DevCloud &cl, const TileInfo &ti
 // first pass: full-stencil least squares of dq_i = q_i - q_p (eq. (11)), and
 // the componentwise max / min of q over the point and its stencil (bounds of
 // the limited reconstruction), stored as offsets from q.  Slot record
-// (double2): q 0..1, position 2.
+// (double2): q 0..1, position 2.  B64 false: the bounds go to the FP32
+// shadow only (a compile-time choice: a run-time test costs the FP64 form a
+// wave of occupancy).
+template <bool B64>
 __global__ void __launch_bounds__(kBlock) k_grad0(DevCloud cl, int cap,
                                                   const double2 *__restrict__ q,
                                                   double2 *__restrict__ g,
@@ -543,7 +546,7 @@ __global__ void __launch_bounds__(kBlock) k_grad0(DevCloud cl, int cap,
             bv[r] = mx[r] - qp[r];
             bv[4 + r] = mn[r] - qp[r];
         }
-        qmm[4 * p + sub] = make_double2(bv[2 * sub], bv[2 * sub + 1]);
+        if (B64) qmm[4 * p + sub] = make_double2(bv[2 * sub], bv[2 * sub + 1]);
         if (sh.qmm32 && sub < 2) sh.qmm32[2 * p + sub] = to_f4(bv + 4 * sub);
     }
 }
@@ -684,8 +687,14 @@ hipError_t launch_grad0(hipStream_t st, const DevCloud &c, int lds_budget, const
                         double2 *g, double2 *qmm, int want_bounds, Shadow sh) {
     const int rec = 3 * (int)sizeof(double2);
     const int cap = lds_cap(c, lds_budget, rec);
-    hipLaunchKernelGGL(k_grad0, dim3(num_flux_tiles(c.n)), dim3(kBlock), (size_t)cap * rec, st, c,
-                       cap, q, g, qmm, want_bounds, sh);
+    if (want_bounds && !qmm) {
+        if (!sh.qmm32) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_grad0<false>, dim3(num_flux_tiles(c.n)), dim3(kBlock),
+                           (size_t)cap * rec, st, c, cap, q, g, qmm, want_bounds, sh);
+    } else {
+        hipLaunchKernelGGL(k_grad0<true>, dim3(num_flux_tiles(c.n)), dim3(kBlock),
+                           (size_t)cap * rec, st, c, cap, q, g, qmm, want_bounds, sh);
+    }
     return hipGetLastError();
 }
 

@@ -485,8 +485,8 @@ constexpr int kGradkLds = 22 * 1024;
 
 // One stage's q-derivatives: first pass + n_inner Jacobi iterations; leaves
 // the final iterate in g[gfin].  In mixed precision the flux reads only the
-// FP32 shadows, so unless fp64_out is set (inspection) the last iterate's
-// FP64 copy is not written.
+// FP32 shadows, so unless fp64_out is set (inspection) neither the last
+// iterate's FP64 copy nor the FP64 bounds are written.
 int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds, bool fp64_out) {
     // the first pass goes to g[2] when inner iterations follow (they read it
     // as g0); the iterates alternate between g[0] and g[1]
@@ -503,7 +503,7 @@ int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds, bool fp64_o
     {
         Timer t(s, 0);
         HIPCHK(s, launch_grad0(s->stream, c, s->prm.grad_lds > 0 ? s->prm.grad_lds : kGrad0Lds,
-                               s->q[s->qcur], s->g[first], s->qmm,
+                               s->q[s->qcur], s->g[first], skip64 ? nullptr : s->qmm,
                                want_bounds ? 1 : 0, sh));
         t.done();
     }
