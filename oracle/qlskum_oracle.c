@@ -383,12 +383,54 @@ void ora_q_derivatives(const ora_cloud *cl, int32_t n_inner, const double *q, do
 /* (phi = 1 when the denominator vanishes; no clamp to 1).              */
 /* ------------------------------------------------------------------ */
 
-static double venkat(double delta, double q, double qmx, double qmn, double eps2)
+double ora_venkat(double delta, double q, double qmx, double qmn, double eps2)
 {
     double D = (delta > 0.0) ? (qmx - q) : (qmn - q);
     double num = (D * D + eps2) + 2.0 * delta * D;
     double den = D * D + 2.0 * delta * delta + delta * D + eps2;
     return (den == 0.0) ? 1.0 : num / den;
+}
+
+/* eps^2 = (K |P_i - P_0|)^3 for the offset (dx, dy) */
+double ora_venkat_eps2(double K, double dx, double dy)
+{
+    double e = K * sqrt(dx * dx + dy * dy);
+    return e * e * e;
+}
+
+/* ------------------------------------------------------------------ */
+/* Modified q of one neighbour entry k of point p, eq. (28):            */
+/*   q~_i = q_i + phi_i delta_i,  q~_0 = q_p + phi_0 delta_0,           */
+/*   delta = -1/2 (dx q_x + dy q_y) at that point,                      */
+/* with phi from the limiter above (phi = 1 when it is off); in the     */
+/* first-order mode q~ = q.                                              */
+/* ------------------------------------------------------------------ */
+
+void ora_modified_q(const ora_cloud *cl, const ora_params *prm, const double *q, const double *g,
+                    const double *qmax, const double *qmin, int64_t p, int64_t k, double qti[4],
+                    double qt0[4])
+{
+    int64_t n = cl->n;
+    int32_t i = cl->idx[k];
+    double dx = cl->x[i] - cl->x[p], dy = cl->y[i] - cl->y[p];
+    double eps2 = 0.0;
+    if (prm->limiter) eps2 = ora_venkat_eps2(prm->venkat_k, dx, dy);
+    for (int r = 0; r < 4; ++r) {
+        if (prm->order == 1) { /* first-order LSKUM: split fluxes of q itself */
+            qti[r] = q[r * n + i];
+            qt0[r] = q[r * n + p];
+            continue;
+        }
+        double di = -0.5 * (dx * g[r * n + i] + dy * g[(4 + r) * n + i]);
+        double d0 = -0.5 * (dx * g[r * n + p] + dy * g[(4 + r) * n + p]);
+        double phii = 1.0, phi0 = 1.0;
+        if (prm->limiter) {
+            phii = ora_venkat(di, q[r * n + i], qmax[r * n + i], qmin[r * n + i], eps2);
+            phi0 = ora_venkat(d0, q[r * n + p], qmax[r * n + p], qmin[r * n + p], eps2);
+        }
+        qti[r] = q[r * n + i] + phii * di;
+        qt0[r] = q[r * n + p] + phi0 * d0;
+    }
 }
 
 /* ------------------------------------------------------------------ */
@@ -431,28 +473,8 @@ int ora_flux_residual(const ora_cloud *cl, const ora_params *prm, const double *
             double dx = cl->x[i] - cl->x[p], dy = cl->y[i] - cl->y[p];
             double ds = dx * tx + dy * ty;
             double dn = dx * nx + dy * ny;
-            double eps2 = 0.0;
-            if (prm->limiter) {
-                double e = prm->venkat_k * sqrt(dx * dx + dy * dy);
-                eps2 = e * e * e;
-            }
             double qti[4], qt0[4];
-            for (int r = 0; r < 4; ++r) {
-                if (prm->order == 1) { /* first-order LSKUM: split fluxes of q itself */
-                    qti[r] = q[r * n + i];
-                    qt0[r] = q[r * n + p];
-                    continue;
-                }
-                double di = -0.5 * (dx * g[r * n + i] + dy * g[(4 + r) * n + i]);
-                double d0 = -0.5 * (dx * g[r * n + p] + dy * g[(4 + r) * n + p]);
-                double phii = 1.0, phi0 = 1.0;
-                if (prm->limiter) {
-                    phii = venkat(di, q[r * n + i], qmax[r * n + i], qmin[r * n + i], eps2);
-                    phi0 = venkat(d0, q[r * n + p], qmax[r * n + p], qmin[r * n + p], eps2);
-                }
-                qti[r] = q[r * n + i] + phii * di;
-                qt0[r] = q[r * n + p] + phi0 * d0;
-            }
+            ora_modified_q(cl, prm, q, g, qmax, qmin, p, k, qti, qt0);
             if (!(qti[3] < 0.0) || !(qt0[3] < 0.0)) { *bad_point = p; return ORA_EPOSITIVITY; }
             double pri[4], pr0[4];
             ora_q_to_prim(qti, gamma, pri);
