@@ -47,7 +47,7 @@ class OracleError(RuntimeError):
 class _Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("mach", C.c_double), ("alpha_deg", C.c_double),
                 ("cfl", C.c_double), ("n_inner", C.c_int32), ("limiter", C.c_int32),
-                ("venkat_k", C.c_double), ("order", C.c_int32)]
+                ("venkat_k", C.c_double), ("order", C.c_int32), ("outer_bc", C.c_int32)]
 
 
 class _Cloud(C.Structure):
@@ -85,9 +85,9 @@ def load(path=_LIB):
     lib.ora_q_derivatives.argtypes = [P(_Cloud), i32, vp, vp, vp, vp]
     lib.ora_flux_residual.argtypes = [P(_Cloud), P(_Params), vp, vp, vp, vp, vp, P(i64)]
     lib.ora_timestep.argtypes = [P(_Cloud), P(_Params), vp, vp]
-    lib.ora_state_update.argtypes = [P(_Cloud), i32, vp, vp, vp, vp]
+    lib.ora_state_update.argtypes = [P(_Cloud), P(_Params), i32, vp, vp, vp, vp]
     lib.ora_rk_stage.argtypes = [i32, i64, vp, vp, vp, vp, vp]
-    lib.ora_residue.argtypes = [P(_Cloud), vp, vp]
+    lib.ora_residue.argtypes = [P(_Cloud), P(_Params), vp, vp]
     lib.ora_evaluate.argtypes = [P(_Cloud), P(_Params), vp, vp, vp, vp, vp, vp, vp, P(i64)]
     lib.ora_run.argtypes = [P(_Cloud), P(_Params), vp, i32, vp, P(i64)]
     lib.ora_forces.argtypes = [P(_Cloud), P(_Params), vp, P(d), P(d)]
@@ -109,11 +109,12 @@ def _p(a):
 
 
 def params(gamma=1.4, mach=0.63, alpha_deg=2.0, cfl=0.2, n_inner=3, limiter=0, venkat_k=5.0,
-           order=2):
+           order=2, outer_bc=0):
     """order 2: modified q of eq. (28) (second order); 1: first-order LSKUM,
-    the split fluxes of q itself."""
+    the split fluxes of q itself.  outer_bc 0: outer points held at the
+    freestream; 1: kinetic outer condition."""
     return dict(gamma=gamma, mach=mach, alpha_deg=alpha_deg, cfl=cfl, n_inner=n_inner,
-                limiter=limiter, venkat_k=venkat_k, order=order)
+                limiter=limiter, venkat_k=venkat_k, order=order, outer_bc=outer_bc)
 
 
 class Oracle:
@@ -190,7 +191,7 @@ class Oracle:
         """residue() of a (4, n) residual array: RMS over interior and wall."""
         R = np.ascontiguousarray(R, np.float64)
         out = np.empty(4)
-        self.lib.ora_residue(C.byref(self._c), _p(R), _p(out))
+        self.lib.ora_residue(C.byref(self._c), C.byref(self._prm), _p(R), _p(out))
         return out
 
     def modified_q(self, q, g, qmax, qmin, p, k):

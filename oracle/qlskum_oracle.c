@@ -56,6 +56,7 @@ typedef struct {
     int32_t n_inner, limiter;
     double venkat_k;
     int32_t order; /* 2: modified q of eq. (28); 1: first order, q~ = q */
+    int32_t outer_bc; /* 0: outer points held at the freestream; 1: kinetic outer condition */
 } ora_params;
 
 typedef struct {
@@ -406,31 +407,34 @@ double ora_venkat_eps2(double K, double dx, double dy)
 /* first-order mode q~ = q.                                              */
 /* ------------------------------------------------------------------ */
 
-void ora_modified_q(const ora_cloud *cl, const ora_params *prm, const double *q, const double *g,
-                    const double *qmax, const double *qmin, int64_t p, int64_t k, double qti[4],
-                    double qt0[4])
+/* q~ of point j shifted by the offset (dx, dy): q_j - 1/2 (dx q_x,j + dy q_y,j),
+ * the increment limited with point j's own bounds and eps from |(dx, dy)|. */
+static void shifted_q(const ora_params *prm, int64_t n, const double *q, const double *g,
+                      const double *qmax, const double *qmin, int64_t j, double dx, double dy,
+                      double out[4])
 {
-    int64_t n = cl->n;
-    int32_t i = cl->idx[k];
-    double dx = cl->x[i] - cl->x[p], dy = cl->y[i] - cl->y[p];
     double eps2 = 0.0;
     if (prm->limiter) eps2 = ora_venkat_eps2(prm->venkat_k, dx, dy);
     for (int r = 0; r < 4; ++r) {
         if (prm->order == 1) { /* first-order LSKUM: split fluxes of q itself */
-            qti[r] = q[r * n + i];
-            qt0[r] = q[r * n + p];
+            out[r] = q[r * n + j];
             continue;
         }
-        double di = -0.5 * (dx * g[r * n + i] + dy * g[(4 + r) * n + i]);
-        double d0 = -0.5 * (dx * g[r * n + p] + dy * g[(4 + r) * n + p]);
-        double phii = 1.0, phi0 = 1.0;
-        if (prm->limiter) {
-            phii = ora_venkat(di, q[r * n + i], qmax[r * n + i], qmin[r * n + i], eps2);
-            phi0 = ora_venkat(d0, q[r * n + p], qmax[r * n + p], qmin[r * n + p], eps2);
-        }
-        qti[r] = q[r * n + i] + phii * di;
-        qt0[r] = q[r * n + p] + phi0 * d0;
+        double d = -0.5 * (dx * g[r * n + j] + dy * g[(4 + r) * n + j]);
+        double phi = 1.0;
+        if (prm->limiter) phi = ora_venkat(d, q[r * n + j], qmax[r * n + j], qmin[r * n + j], eps2);
+        out[r] = q[r * n + j] + phi * d;
     }
+}
+
+void ora_modified_q(const ora_cloud *cl, const ora_params *prm, const double *q, const double *g,
+                    const double *qmax, const double *qmin, int64_t p, int64_t k, double qti[4],
+                    double qt0[4])
+{
+    int32_t i = cl->idx[k];
+    double dx = cl->x[i] - cl->x[p], dy = cl->y[i] - cl->y[p];
+    shifted_q(prm, cl->n, q, g, qmax, qmin, i, dx, dy, qti);
+    shifted_q(prm, cl->n, q, g, qmax, qmin, p, dx, dy, qt0);
 }
 
 /* ------------------------------------------------------------------ */
@@ -444,7 +448,18 @@ void ora_modified_q(const ora_cloud *cl, const ora_params *prm, const double *q,
 /*   Det   = sum ds^2 sum dn^2 - (sum ds dn)^2   (sums over the stencil) */
 /* Interior: R = dGs+/ds + dGs-/ds + dGn+/dn + dGn-/dn (eq. (12)).      */
 /* Wall (normal into the fluid): the n+ term, whose stencil lies in the */
-/* body, is dropped.  Outer points carry no residual.                   */
+/* body, is dropped.  Outer points carry no residual when they are held */
+/* at the freestream (outer_bc 0).  Kinetic outer condition (outer_bc   */
+/* 1; the normal points away from the body, to the far field): the own  */
+/* n- stencil would lie outside the domain, where the molecules that    */
+/* enter come from the freestream Maxwellian.  It is replaced by the    */
+/* mirror image of the n+ stencil through the point's tangent line,     */
+/* (ds, dn) -> (ds, -dn), whose points hold the uniform freestream      */
+/* (q~ = q_inf, no gradient); the point's own modified state for each   */
+/* mirrored entry is shifted by the mirrored offset.  So               */
+/*   R = dGs+/ds + dGs-/ds + dGn+/dn + dGn-/dn|mirror,                  */
+/* with dGn-/dn|mirror the Cramer derivative of eq. (13) over the       */
+/* mirrored offsets of Gn-(q_inf) - Gn-(q~_0').                          */
 /* ------------------------------------------------------------------ */
 
 typedef struct {
@@ -457,10 +472,19 @@ int ora_flux_residual(const ora_cloud *cl, const ora_params *prm, const double *
 {
     int64_t n = cl->n;
     double gamma = prm->gamma;
+    int kobc = prm->outer_bc == 1;
+    double qinf[4], prinf[4];
+    {
+        const double pi = 3.14159265358979323846;
+        double al = prm->alpha_deg * pi / 180.0;
+        double pr[4] = {1.0, prm->mach * cos(al), prm->mach * sin(al), 1.0 / gamma};
+        ora_prim_to_q(pr, gamma, qinf);
+        ora_q_to_prim(qinf, gamma, prinf);
+    }
     *bad_point = -1;
     for (int64_t p = 0; p < n; ++p) {
         for (int r = 0; r < 4; ++r) R[r * n + p] = 0.0;
-        if (cl->kind[p] == KIND_OUTER) continue;
+        if (cl->kind[p] == KIND_OUTER && !kobc) continue;
         double nx = cl->nx[p], ny = cl->ny[p];
         double tx = ny, ty = -nx;
         bucket bk[4];
@@ -469,6 +493,7 @@ int ora_flux_residual(const ora_cloud *cl, const ora_params *prm, const double *
             int32_t i = cl->idx[k];
             uint8_t f = cl->flag[k];
             if (cl->kind[p] == KIND_WALL) f &= (uint8_t)~SPLIT_N_PLUS;
+            if (cl->kind[p] == KIND_OUTER) f &= (uint8_t)~SPLIT_N_MINUS;
             if (f == 0) continue;
             double dx = cl->x[i] - cl->x[p], dy = cl->y[i] - cl->y[p];
             double ds = dx * tx + dy * ty;
@@ -505,6 +530,35 @@ int ora_flux_residual(const ora_cloud *cl, const ora_params *prm, const double *
                 }
             }
         }
+        if (cl->kind[p] == KIND_OUTER) {
+            /* the mirrored n+ stencil at the freestream replaces n- */
+            memset(&bk[3], 0, sizeof bk[3]);
+            double Ginf[4];
+            ora_split_flux(prinf, nx, ny, -1, gamma, Ginf);
+            for (int32_t k = cl->ptr[p]; k < cl->ptr[p + 1]; ++k) {
+                if (!(cl->flag[k] & SPLIT_N_PLUS)) continue;
+                int32_t i = cl->idx[k];
+                double dx = cl->x[i] - cl->x[p], dy = cl->y[i] - cl->y[p];
+                double ds = dx * tx + dy * ty;
+                double dn = -(dx * nx + dy * ny);      /* mirrored */
+                double mx = ds * tx + dn * nx, my = ds * ty + dn * ny;
+                double qt0[4], pr0[4], G0[4];
+                shifted_q(prm, n, q, g, qmax, qmin, p, mx, my, qt0);
+                if (!(qt0[3] < 0.0)) { *bad_point = p; return ORA_EPOSITIVITY; }
+                ora_q_to_prim(qt0, gamma, pr0);
+                for (int r = 0; r < 4; ++r)
+                    if (!isfinite(pr0[r])) { *bad_point = p; return ORA_EPOSITIVITY; }
+                ora_split_flux(pr0, nx, ny, -1, gamma, G0);
+                bk[3].ss += ds * ds;
+                bk[3].sn += ds * dn;
+                bk[3].nn += dn * dn;
+                for (int r = 0; r < 4; ++r) {
+                    double dG = Ginf[r] - G0[r];
+                    bk[3].sG[r] += ds * dG;
+                    bk[3].nG[r] += dn * dG;
+                }
+            }
+        }
         double Rp[4] = {0, 0, 0, 0};
         for (int b = 0; b < 4; ++b) {
             if (b == 2 && cl->kind[p] == KIND_WALL) continue;
@@ -528,7 +582,8 @@ int ora_flux_residual(const ora_cloud *cl, const ora_params *prm, const double *
 /*   rk2: U2 = U1 + dt/2 L(U1)                                          */
 /*   rk3: U3 = 2/3 Un + 1/3 (U2 + dt/2 L(U2))                           */
 /*   rk4: U4 = U3 + dt/2 L(U3)                                          */
-/* Applied pointwise to m values; the update of one point.              */
+/* Applied pointwise to m values; the update of one point.  Outer points  */
+/* are held at the freestream unless the kinetic outer condition is on.  */
 /* ------------------------------------------------------------------ */
 
 void ora_rk_stage(int32_t rk, int64_t m, const double *un, const double *u, const double *r,
@@ -542,12 +597,12 @@ void ora_rk_stage(int32_t rk, int64_t m, const double *un, const double *u, cons
     }
 }
 
-void ora_state_update(const ora_cloud *cl, int32_t rk, const double *Un, double *U,
-                      const double *R, const double *dt)
+void ora_state_update(const ora_cloud *cl, const ora_params *prm, int32_t rk, const double *Un,
+                      double *U, const double *R, const double *dt)
 {
     int64_t n = cl->n;
     for (int64_t p = 0; p < n; ++p) {
-        if (cl->kind[p] == KIND_OUTER) continue; /* held at the far-field state */
+        if (cl->kind[p] == KIND_OUTER && prm->outer_bc != 1) continue; /* held */
         for (int c = 0; c < 4; ++c) {
             double v;
             ora_rk_stage(rk, 1, &Un[c * n + p], &U[c * n + p], &R[c * n + p], &dt[p], &v);
@@ -558,16 +613,17 @@ void ora_state_update(const ora_cloud *cl, int32_t rk, const double *Un, double 
 }
 
 /* ------------------------------------------------------------------ */
-/* Algorithm 1, residue(): root mean square over the updated (interior  */
-/* and wall) points of each component of the first stage's residual.  */
+/* Algorithm 1, residue(): root mean square over the updated points     */
+/* (interior and wall; outer too under the kinetic outer condition) of   */
+/* each component of the first stage's residual.                        */
 /* ------------------------------------------------------------------ */
 
-void ora_residue(const ora_cloud *cl, const double *R, double res[4])
+void ora_residue(const ora_cloud *cl, const ora_params *prm, const double *R, double res[4])
 {
     int64_t n = cl->n, m = 0;
     double s[4] = {0, 0, 0, 0};
     for (int64_t p = 0; p < n; ++p) {
-        if (cl->kind[p] == KIND_OUTER) continue;
+        if (cl->kind[p] == KIND_OUTER && prm->outer_bc != 1) continue;
         m++;
         for (int c = 0; c < 4; ++c) s[c] += R[c * n + p] * R[c * n + p];
     }
@@ -618,8 +674,8 @@ int ora_run(const ora_cloud *cl, const ora_params *prm, double *U, int32_t n_ite
             ora_q_derivatives(cl, prm->n_inner, q, g, qmax, qmin);
             st = ora_flux_residual(cl, prm, q, g, qmax, qmin, R, bad_point);
             if (st) goto done;
-            if (rk == 1 && res_hist) ora_residue(cl, R, &res_hist[4 * (int64_t)it]);
-            ora_state_update(cl, rk, Un, U, R, dt);
+            if (rk == 1 && res_hist) ora_residue(cl, prm, R, &res_hist[4 * (int64_t)it]);
+            ora_state_update(cl, prm, rk, Un, U, R, dt);
         }
     }
 done:

@@ -16,7 +16,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "qlskum_oracle.c")
-PINS = ["tests/test_oracle_pins_aux.py"]
+PINS = ["tests/test_oracle_pins_aux.py", "tests/test_oracle_pins_kobc.py"]
 
 PLANTS = {
     "timestep: largest distance": (
@@ -26,11 +26,11 @@ PLANTS = {
     "timestep: CFL dropped": (
         "dt[p] = prm->cfl * dmin / (speed + c);", "dt[p] = dmin / (speed + c);"),
     "residue: outer points counted": (
-        "        if (cl->kind[p] == KIND_OUTER) continue;\n        m++;",
-        "        m++;\n        if (cl->kind[p] == KIND_OUTER) continue;"),
+        "        if (cl->kind[p] == KIND_OUTER && prm->outer_bc != 1) continue;\n        m++;",
+        "        m++;\n        if (cl->kind[p] == KIND_OUTER && prm->outer_bc != 1) continue;"),
     "residue: outer points summed": (
-        "        if (cl->kind[p] == KIND_OUTER) continue;\n        m++;",
-        "        if (cl->kind[p] == KIND_OUTER) {}\n        m++;"),
+        "        if (cl->kind[p] == KIND_OUTER && prm->outer_bc != 1) continue;\n        m++;",
+        "        if (cl->kind[p] == KIND_OUTER && prm->outer_bc != 1) {}\n        m++;"),
     "forces: one-sided arc length": ("double ds = 0.5 * (ln + lp);", "double ds = ln;"),
     "forces: sign of the pressure force": (
         "F[h][0] += -(prim[3] - pinf) * cl->nx[p] * ds;",
@@ -58,12 +58,30 @@ PLANTS = {
     "limiter: eps^2 = (K d)^2": ("return e * e * e;", "return e * e;"),
     "limiter: eps from dx only": (
         "double e = K * sqrt(dx * dx + dy * dy);", "double e = K * sqrt(dx * dx);"),
-    "eq. (28): neighbour's bounds at p": (
-        "phi0 = ora_venkat(d0, q[r * n + p], qmax[r * n + p], qmin[r * n + p], eps2);",
-        "phi0 = ora_venkat(d0, q[r * n + p], qmax[r * n + i], qmin[r * n + i], eps2);"),
-    "eq. (28): sign of the shift at p": (
-        "double d0 = -0.5 * (dx * g[r * n + p] + dy * g[(4 + r) * n + p]);",
-        "double d0 = 0.5 * (dx * g[r * n + p] + dy * g[(4 + r) * n + p]);"),
+    "eq. (28): bounds swapped in the limited shift": (
+        "phi = ora_venkat(d, q[r * n + j], qmax[r * n + j], qmin[r * n + j], eps2);",
+        "phi = ora_venkat(d, q[r * n + j], qmin[r * n + j], qmax[r * n + j], eps2);"),
+    "eq. (28): sign of the shift": (
+        "double d = -0.5 * (dx * g[r * n + j] + dy * g[(4 + r) * n + j]);",
+        "double d = 0.5 * (dx * g[r * n + j] + dy * g[(4 + r) * n + j]);"),
+    "eq. (28): full instead of half shift": (
+        "double d = -0.5 * (dx * g[r * n + j] + dy * g[(4 + r) * n + j]);",
+        "double d = -1.0 * (dx * g[r * n + j] + dy * g[(4 + r) * n + j]);"),
+    "eq. (28): point's own shift with the neighbour's derivatives": (
+        "shifted_q(prm, cl->n, q, g, qmax, qmin, p, dx, dy, qt0);",
+        "shifted_q(prm, cl->n, q, g, qmax, qmin, i, dx, dy, qt0); "
+        "for (int r = 0; r < 4; ++r) qt0[r] += q[r * cl->n + p] - q[r * cl->n + i];"),
+    "outer condition: mirror not applied": (
+        "double dn = -(dx * nx + dy * ny);      /* mirrored */",
+        "double dn = (dx * nx + dy * ny);      /* mirrored */"),
+    "outer condition: entering flux G+ instead of G-": (
+        "ora_split_flux(prinf, nx, ny, -1, gamma, Ginf);", "ora_split_flux(prinf, nx, ny, 1, gamma, Ginf);"),
+    "outer condition: own state not shifted by the mirrored offset": (
+        "shifted_q(prm, n, q, g, qmax, qmin, p, mx, my, qt0);",
+        "shifted_q(prm, n, q, g, qmax, qmin, p, dx, dy, qt0);"),
+    "outer condition: outer points not updated": (
+        "if (cl->kind[p] == KIND_OUTER && prm->outer_bc != 1) continue; /* held */",
+        "if (cl->kind[p] == KIND_OUTER) continue; /* held */"),
 }
 
 
