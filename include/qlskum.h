@@ -90,14 +90,28 @@ typedef struct {
     int32_t flux_split;/* 0: one fused flux sweep; 1 (FP64, second order): the
                          s-direction split fluxes in one launch and the
                          n-direction ones with the update in a second (fewer
-                         registers per launch, the reconstruction done twice;
-                         the residual's summation grouping changes in the
-                         last bits)                                          */
+                         registers per launch, the reconstruction done twice);
+                         2 (FP64, second order): one launch per split stencil
+                         s+, s-, n+, n- (the kernel splitting of the paper's
+                         sec. 5), the last with the update.  The residual's
+                         summation grouping changes in the last bits       */
+    int32_t outer_bc; /* 0: outer points held at the freestream (Dirichlet);
+                         1: kinetic outer condition (sec. 2.1 combines the
+                         scheme with it; its formula is left to a reference):
+                         outer points are updated like interior points, with
+                         their n- split stencil, which would lie beyond the
+                         far field, replaced by the mirror image of their n+
+                         stencil through the point's tangent line, whose
+                         points hold the freestream Maxwellian.  Outer
+                         normals point to the far field.  Outer points then
+                         count in the residual norm.  Needs non-singular
+                         s+, s-, n+ stencils at every outer point
+                         (QL_ESINGULAR otherwise, at upload or here)      */
 } ql_params;
 
 /* Fill *p with the defaults: gamma 1.4, M 0.63, alpha 2, CFL 0.2, 3 inner
  * iterations, limiter off (K = 5), FP64, Hilbert reorder, default LDS
- * budgets (0), second order, fused flux sweep. */
+ * budgets (0), second order, fused flux sweep, outer points held. */
 void ql_default_params(ql_params *p);
 
 /* Create a solver on HIP device `device`.  `hip_stream` is a hipStream_t
@@ -125,7 +139,8 @@ int ql_destroy(ql_solver *s);
  * the device classifies entries, precomputes least-squares factors and
  * checks that every matrix the scheme inverts is non-singular: the full
  * stencil of every point and each split stencil entering the residual
- * (interior: all four; wall: s+, s-, n-), each needing >= 2 points and
+ * (interior: all four; wall: s+, s-, n-; outer, with params.outer_bc = 1
+ * only: s+, s-, n+), each needing >= 2 points and
  * det > 1e-12 (sum ds^2 + sum dn^2)^2.
  * Errors: QL_EINVAL (malformed input), QL_ESINGULAR (message names the
  * point), QL_ENOMEM, QL_EDEVICE.  Any previous cloud and state are dropped. */
@@ -152,7 +167,8 @@ int ql_set_state(ql_solver *s, const double *U, int32_t mem, int32_t project_wal
  * local time step, four stages of four-stage third-order SSP Runge-Kutta,
  * and the residual norm of the first stage's residual.  res_hist (host,
  * nullable) receives [n_iter][ncase][4] residual norms (root mean square
- * over the interior and wall points of each component; ncase = 1 unless
+ * over the interior and wall points of each component, and the outer points
+ * under the kinetic outer condition; ncase = 1 unless
  * the cloud came from ql_batch_upload).  Enqueues on the solver's
  * stream and synchronises once at the end.
  * Errors: QL_ESTATE, QL_EPOSITIVITY / QL_ENONFINITE (first point of the

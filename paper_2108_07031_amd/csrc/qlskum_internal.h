@@ -46,12 +46,18 @@ struct DevCloud {
     const int *case_of;
     const uint8_t *case_active;
     const uint8_t *tile_active;
+    // conserved freestream of each case [ncase][4] (the kinetic outer
+    // condition's far-field Maxwellian)
+    const double *uinf;
 };
 
 struct FlowParams {
     double gamma, gm1inv, cfl, venkat_k;
     int n_inner, limiter;
     int order;  // 2: modified q of eq. (28); 1: first order (q~ = q)
+    // 1: kinetic outer condition (outer points updated; their n- stencil is
+    // the mirror image of n+ holding the freestream); 0: outer points held
+    int kobc;
     // m = 2/(gamma-1) when it is a small integer (5 for gamma = 1.4), so that
     // beta^(-1/(gamma-1)) = (1/sqrt(beta))^m needs no logarithm; 0 otherwise
     int sqrt_pow;
@@ -70,9 +76,12 @@ struct Shadow {
 int num_blocks(int n);
 int num_flux_tiles(int n);
 
+// err_outer receives singular split stencils of outer points (used only by
+// the kinetic outer condition), err every other singular matrix.
 hipError_t launch_setup(hipStream_t st, int n, const double2 *xy, const double2 *nrm,
                         const uint8_t *kind, const int *ptr, const int *idx, uint8_t *flag,
-                        int classify, double *lsw, double *lsi, double *dmin, int *err);
+                        int classify, double *lsw, double *lsi, double *dmin, int *err,
+                        int *err_outer);
 hipError_t launch_freestream(hipStream_t st, int n, const double2 *nrm, const uint8_t *kind,
                              const int *case_of, const double *uinf, double *U);
 hipError_t launch_permute_state(hipStream_t st, int n, const double *Uuser, const int *perm,
@@ -93,12 +102,14 @@ hipError_t launch_gradk(hipStream_t st, const DevCloud &c, int lds_budget, const
 // stage 0: evaluate only (writes Rout); stages 1..4: residual + SSP-RK stage.
 // q32next (nullable) receives the FP32 shadow of the new q.  lds_budget =
 // bytes of LDS a workgroup may stage its tile image in (tiles with larger
-// images read from memory).  Rpart (nullable, [4][n]): split the work into
-// an s-direction launch and an n-direction + update launch.
+// images read from memory).  split: 0 one fused launch; 2 an s-direction
+// launch and an n-direction + update launch; 4 one launch per split stencil
+// (s+, s-, n+, n- + update).  Rpart: two [4][n] buffers of partial sums
+// (split > 0 only).
 hipError_t launch_flux(hipStream_t st, const DevCloud &c, const FlowParams &fp, int stage,
                        int lds_budget, const double2 *q, const double2 *g, const double2 *qmm,
                        double *U, double *Un, double *dt, double2 *qnext, double *Rout,
-                       float4 *q32next, int *err, double *Rpart);
+                       float4 *q32next, int *err, int split, double *const Rpart[2]);
 // mixed precision: reconstruction, limiter and split fluxes in FP32 from the
 // shadows q32, g32, qmm32; weights, residual sums and the update in FP64.
 hipError_t launch_flux_mixed(hipStream_t st, const DevCloud &c, const FlowParams &fp, int stage,

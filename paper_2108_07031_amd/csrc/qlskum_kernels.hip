@@ -23,6 +23,7 @@
 
 #include <climits>
 #include <cmath>
+#include <type_traits>
 
 namespace ql {
 
@@ -122,7 +123,8 @@ __global__ void __launch_bounds__(kBlock) k_setup(int n, const double2 *__restri
                                                   const int *__restrict__ idx, uint8_t *flag,
                                                   int classify, double *__restrict__ lsw,
                                                   double *__restrict__ lsi,
-                                                  double *__restrict__ dmin, int *err) {
+                                                  double *__restrict__ dmin, int *err,
+                                                  int *err_outer) {
 #pragma clang fp contract(off)
     const int p = point_id();
     if (p >= n) return;
@@ -169,28 +171,42 @@ __global__ void __launch_bounds__(kBlock) k_setup(int n, const double2 *__restri
     lsi[3 * p + 1] = b / D;
     lsi[3 * p + 2] = a / D;
     const uint8_t kd = kind[p];
+    // An outer point's factors serve the kinetic outer condition only: its
+    // s+, s- and n+ stencils are its own; its n- stencil is the mirror image
+    // of n+ through the tangent line, (ds, dn) -> (ds, -dn), whose sums are
+    // (Sss, -Ssn, Snn) of n+ -- the n- slot holds (Sss/Det, -Ssn/Det) of n+.
+    // A singular outer stencil goes to err_outer, so that a cloud stays
+    // usable with the outer points held at the freestream.
+    bool bad_outer = false;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        const double det = ss[s] * nn[s] - sn[s] * sn[s];
-        const double sc = ss[s] + nn[s];
-        const bool used = (kd == kInterior) || (kd == kWall && s != 2);
+        const int m = (kd == kOuter && s == 3) ? 2 : s;  // stencil whose sums serve slot s
+        const double det = ss[m] * nn[m] - sn[m] * sn[m];
+        const double sc = ss[m] + nn[m];
+        const bool used = (kd == kInterior) || (kd == kWall && s != 2) || kd == kOuter;
         double f0 = 0.0, f1 = 0.0;
         if (used) {
-            if (cnt[s] < 2 || !(det > 1e-12 * sc * sc)) bad = true;
-            f0 = ((s < 2) ? nn[s] : ss[s]) / det;
-            f1 = sn[s] / det;
+            if (cnt[m] < 2 || !(det > 1e-12 * sc * sc)) {
+                if (kd == kOuter) bad_outer = true;
+                else bad = true;
+            }
+            f0 = ((s < 2) ? nn[m] : ss[m]) / det;
+            f1 = sn[m] / det;
+            if (m != s) f1 = -f1;
         }
         lsw[8 * p + 2 * s] = f0;
         lsw[8 * p + 2 * s + 1] = f1;
     }
     if (bad) report(err, p, kErrSingular);
+    if (bad_outer) report(err_outer, p, kErrSingular);
 }
 
 hipError_t launch_setup(hipStream_t st, int n, const double2 *xy, const double2 *nrm,
                         const uint8_t *kind, const int *ptr, const int *idx, uint8_t *flag,
-                        int classify, double *lsw, double *lsi, double *dmin, int *err) {
+                        int classify, double *lsw, double *lsi, double *dmin, int *err,
+                        int *err_outer) {
     hipLaunchKernelGGL(k_setup, dim3(num_blocks(n)), dim3(kBlock), 0, st, n, xy, nrm, kind, ptr,
-                       idx, flag, classify, lsw, lsi, dmin, err);
+                       idx, flag, classify, lsw, lsi, dmin, err, err_outer);
     return hipGetLastError();
 }
 
@@ -851,8 +867,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 // depends only on its data and on the order of its entries, never on the code
 // path that gathered them.  Returns false when a modified state has no
 // Maxwellian.  FIRST: first-order scheme, the split fluxes of q itself.
-// DIRS: the split directions evaluated (1 s, 2 n, 3 both).
-template <bool LIMITER, int POW, bool FIRST, int DIRS = 3>
+// M: the split stencils evaluated (Split bits; 15 all four).  The caller
+// masks f with M, so a direction is evaluated when M holds either half.
+template <bool LIMITER, int POW, bool FIRST, int M = 15>
 __device__ __forceinline__ bool flux_entry(uint8_t f, double dx, double dy, double2 N,
                                            const double qi[4], const double gi[8],
                                            const double bi[8], const double qp[4],
@@ -898,7 +915,7 @@ __device__ __forceinline__ bool flux_entry(uint8_t f, double dx, double dy, doub
     // independent straight-line work the scheduler can interleave
     double Gs[2][4], Gn[2][4];
     double ws = 0.0, wn = 0.0;
-    if (DIRS & 1) {
+    if (M & (kSPlus | kSMinus)) {
         const bool plus = (f & kSPlus) != 0;
         const double sg = plus ? 1.0 : -1.0;
         ws = (f & (kSPlus | kSMinus)) ? fma(ds, plus ? w[0] : w[2], -(dn * (plus ? w[1] : w[3])))
@@ -906,7 +923,7 @@ __device__ __forceinline__ bool flux_entry(uint8_t f, double dx, double dy, doub
         split_flux(si, tx, ty, sg, Gs[0]);
         split_flux(s0, tx, ty, sg, Gs[1]);
     }
-    if (DIRS & 2) {
+    if (M & (kNPlus | kNMinus)) {
         const bool plus = (f & kNPlus) != 0;
         const double sg = plus ? 1.0 : -1.0;
         wn = (f & (kNPlus | kNMinus)) ? fma(dn, plus ? w[4] : w[6], -(ds * (plus ? w[5] : w[7])))
@@ -914,14 +931,73 @@ __device__ __forceinline__ bool flux_entry(uint8_t f, double dx, double dy, doub
         split_flux(si, N.x, N.y, sg, Gn[0]);
         split_flux(s0, N.x, N.y, sg, Gn[1]);
     }
-    if (DIRS & 1) {
+    if (M & (kSPlus | kSMinus)) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) R[r] = fma(ws, Gs[0][r] - Gs[1][r], R[r]);
     }
-    if (DIRS & 2) {
+    if (M & (kNPlus | kNMinus)) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) R[r] = fma(wn, Gn[0][r] - Gn[1][r], R[r]);
     }
+    return ok;
+}
+
+// Kinetic outer condition, one n+ entry (offset (dx, dy) from outer point p)
+// of p's mirrored n- stencil: the mirror image of the neighbour through p's
+// tangent line, at offset (ds, -dn) in p's frame, holds the freestream, so
+// its modified state is q_inf and its split flux G_inf = Gn-(q_inf) (given);
+// p's own modified state is shifted by the mirrored offset as in eq. (28).
+// Adds w (G_inf - Gn-(q~_p)) with w the mirrored stencil's n-derivative
+// weight (k_setup stores the mirrored factors in p's n- slot).
+template <bool LIMITER, int POW, bool FIRST>
+__device__ __forceinline__ bool mirror_entry(double dx, double dy, double2 N, const double qp[4],
+                                             const double gp[8], const double bp[8],
+                                             const double w[8], const double Ginf[4],
+                                             const FlowParams &fp, double R[4]) {
+#pragma clang fp contract(off)
+    const double tx = N.y, ty = -N.x;
+    const double ds = fma(dx, tx, dy * ty);
+    const double dm = -fma(dx, N.x, dy * N.y);
+    const double mx = fma(ds, tx, dm * N.x), my = fma(ds, ty, dm * N.y);
+    double qt0[4];
+    if (FIRST) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) qt0[r] = qp[r];
+    } else if (LIMITER) {
+        const double e = fp.venkat_k * fast_sqrt(fma(mx, mx, my * my));
+        const double eps2 = fmax((e * e) * e, 1e-300);
+        const double hx = -0.5 * mx, hy = -0.5 * my;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double d0 = fma(hx, gp[r], hy * gp[4 + r]);
+            qt0[r] = fma(venkat(d0, bp[r], bp[4 + r], eps2), d0, qp[r]);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) qt0[r] = fma(-0.5, fma(mx, gp[r], my * gp[4 + r]), qp[r]);
+    }
+    Prim s0;
+    const bool ok = q_to_prim<POW>(qt0, fp, s0);
+    double G0[4];
+    split_flux(s0, N.x, N.y, -1.0, G0);
+    const double wm = fma(dm, w[6], -(ds * w[7]));
+#pragma unroll
+    for (int r = 0; r < 4; ++r) R[r] = fma(wm, Ginf[r] - G0[r], R[r]);
+    return ok;
+}
+
+// Gn-(q_inf) along the unit normal N for the case's conserved freestream u
+// (the same q -> primitive -> split-flux path as every modified state, so a
+// freestream state gives bitwise equal fluxes).
+template <int POW>
+__device__ __forceinline__ bool freestream_flux(const double *u, double2 N, const FlowParams &fp,
+                                                double G[4]) {
+    const double v[4] = {u[0], u[1], u[2], u[3]};
+    double qi[4];
+    bool ok = cons_to_q(v, fp, qi) == kErrNone;
+    Prim si;
+    ok &= q_to_prim<POW>(qi, fp, si);
+    split_flux(si, N.x, N.y, -1.0, G);
     return ok;
 }
 
@@ -980,12 +1056,17 @@ __device__ __forceinline__ void rk_update(const DevCloud &cl, const FlowParams &
 // memory (a branch uniform across the workgroup), with the same arithmetic.
 //
 // stage 0: evaluate R only (into Rout).  stage 1..4: residual + rk_update;
-// stage 1 also writes R to Rout for the residual norm.  Outer and frozen
-// points are held (q copied to qnext) and carry R = 0.
+// stage 1 also writes R to Rout for the residual norm.  Frozen points, and
+// outer points unless KOBC, are held (q copied to qnext) and carry R = 0.
+// Kinetic outer condition (fp.kobc): outer points take their s+, s-, n+
+// terms like any point and are updated; the launch that holds n- (M) adds
+// the mirrored n- term of mirror_entry (template flag KOBC = fp.kobc there).
+// M: the split stencils of this launch (15: all; split launches add the
+// other stencils' partial sums Rin).
 // ---------------------------------------------------------------------------
 int num_flux_tiles(int n) { return (n + kFluxTile - 1) / kFluxTile; }
 
-template <bool LIMITER, int POW, bool FIRST, int DIRS>
+template <bool LIMITER, int POW, bool FIRST, int M, bool KOBC>
 // Held to 3 waves per SIMD (at most 168 VGPRs), which the straight-line
 // two-direction body of flux_entry would otherwise exceed.
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
@@ -1044,7 +1125,12 @@ k_flux(DevCloud cl, FlowParams fp, int stage, int cap,
     if (j < nown) {
         kd = cl.kind[p];
         const bool frozen = cl.case_active && !cl.case_active[cl.case_of[p]];
-        live = kd != kOuter && !frozen;
+        // outer points are live under the kinetic outer condition: KOBC
+        // launches, and split launches without the n- stencil (whose
+        // template flag stays false) when fp.kobc is set
+        bool outer_live = KOBC;
+        if constexpr (!KOBC && !(M & kNMinus)) outer_live = fp.kobc != 0;
+        live = (outer_live || kd != kOuter) && !frozen;
     }
     double2 N = make_double2(0.0, 0.0);
     if (live) {
@@ -1072,10 +1158,12 @@ k_flux(DevCloud cl, FlowParams fp, int stage, int cap,
         }
 #pragma unroll
         for (int m = 0; m < 8; ++m) w[m] = cl.lsw[8 * p + m];
-        constexpr uint8_t kDirMask = (DIRS == 1)   ? uint8_t(kSPlus | kSMinus)
-                                     : (DIRS == 2) ? uint8_t(kNPlus | kNMinus)
-                                                   : uint8_t(0xff);
-        const uint8_t fmask = ((kd == kWall) ? uint8_t(~kNPlus) : uint8_t(0xff)) & kDirMask;
+        // walls drop n+ (its stencil lies in the body), outer points n- (it
+        // lies beyond the far field; the mirrored term below replaces it)
+        uint8_t fmask = ((kd == kWall) ? uint8_t(~kNPlus) : uint8_t(0xff)) & uint8_t(M);
+        if constexpr (KOBC) {
+            if (kd == kOuter) fmask &= uint8_t(~kNMinus);
+        }
         const int k1 = cl.ptr[p + 1];
         bool ok = true;
 #pragma unroll 2
@@ -1104,8 +1192,21 @@ k_flux(DevCloud cl, FlowParams fp, int stage, int cap,
                 if (LIMITER) load8(qmm, i, bi);
                 Q = cl.xy[i];
             }
-            ok &= flux_entry<LIMITER, POW, FIRST, DIRS>(f, Q.x - P.x, Q.y - P.y, N, qi, gi, bi, qp,
-                                                        gp, bp, w, fp, R);
+            ok &= flux_entry<LIMITER, POW, FIRST, M>(f, Q.x - P.x, Q.y - P.y, N, qi, gi, bi, qp,
+                                                     gp, bp, w, fp, R);
+        }
+        if constexpr (KOBC && (M & kNMinus)) {
+            if (kd == kOuter) {
+                double Ginf[4];
+                ok &= freestream_flux<POW>(cl.uinf + 4 * cl.case_of[p], N, fp, Ginf);
+                for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
+                    if (!(cl.flag[k] & kNPlus)) continue;
+                    const double2 Q = in_lds ? lds[kRec * (int)cl.flidx[k] + kRec - 1]
+                                             : cl.xy[cl.idx[k]];
+                    ok &= mirror_entry<LIMITER, POW, FIRST>(Q.x - P.x, Q.y - P.y, N, qp, gp, bp,
+                                                            w, Ginf, fp, R);
+                }
+            }
         }
         if (!ok) report(err, p, kErrPositivity);
     }
@@ -1136,38 +1237,71 @@ k_flux(DevCloud cl, FlowParams fp, int stage, int cap,
     if (stage > 0) rk_update(cl, fp, stage, p, kd, N, R, U, Un, dt, qnext, q32next, err);
 }
 
+namespace {
+
+template <bool B>
+using BoolC = std::integral_constant<bool, B>;
+template <int V>
+using IntC = std::integral_constant<int, V>;
+
+// call f(BoolC<limiter>, IntC<pow>, BoolC<kobc>) for the run-time flags
+// (pow: 5 for gamma = 1.4, else the general form 0)
+template <class F>
+void dispatch_flow(const FlowParams &fp, F &&f) {
+    auto with_pow = [&](auto lim, auto kobc) {
+        if (fp.sqrt_pow == 5) f(lim, IntC<5>{}, kobc);
+        else f(lim, IntC<0>{}, kobc);
+    };
+    auto with_kobc = [&](auto lim) {
+        if (fp.kobc) with_pow(lim, BoolC<true>{});
+        else with_pow(lim, BoolC<false>{});
+    };
+    if (fp.limiter) with_kobc(BoolC<true>{});
+    else with_kobc(BoolC<false>{});
+}
+
+}  // namespace
+
 hipError_t launch_flux(hipStream_t st, const DevCloud &c, const FlowParams &fp, int stage,
                        int lds_budget, const double2 *q, const double2 *g, const double2 *qmm,
                        double *U, double *Un, double *dt, double2 *qnext, double *Rout,
-                       float4 *q32next, int *err, double *Rpart) {
+                       float4 *q32next, int *err, int split, double *const Rpart[2]) {
     const bool first = fp.order == 1;
     const int rec = (first ? 3 : fp.limiter ? 11 : 7) * (int)sizeof(double2);
     const int cap = lds_cap(c, lds_budget, rec);
     const size_t shmem = (size_t)cap * rec;
     const dim3 grid(num_flux_tiles(c.n)), block(kBlock);
-#define QL_FLUX_LAUNCH(LIM, POW, FIRST, DIRS, STAGE, RIN, ROUT)                            \
-    hipLaunchKernelGGL((k_flux<LIM, POW, FIRST, DIRS>), grid, block, shmem, st, c, fp, STAGE, \
-                       cap, RIN, q, g, qmm, U, Un, dt, qnext, ROUT, q32next, err)
-    // Rpart != null: the s directions in one launch (into Rpart), the n
-    // directions and the update in a second one (fewer registers each)
-#define QL_FLUX_DISPATCH(LIM, POW)                                                       \
-    if (Rpart) {                                                                         \
-        QL_FLUX_LAUNCH(LIM, POW, false, 1, 0, (const double *)nullptr, Rpart);         \
-        QL_FLUX_LAUNCH(LIM, POW, false, 2, stage, (const double *)Rpart, Rout);        \
-    } else {                                                                             \
-        QL_FLUX_LAUNCH(LIM, POW, false, 3, stage, (const double *)nullptr, Rout);      \
+    auto go = [&](auto kern, int stg, const double *rin, double *rout) {
+        hipLaunchKernelGGL(kern, grid, block, shmem, st, c, fp, stg, cap, rin, q, g, qmm, U, Un,
+                           dt, qnext, rout, q32next, err);
+    };
+    if (first) {  // first order: one fused launch
+        if (fp.sqrt_pow == 5) {
+            if (fp.kobc) go(k_flux<false, 5, true, 15, true>, stage, nullptr, Rout);
+            else go(k_flux<false, 5, true, 15, false>, stage, nullptr, Rout);
+        } else {
+            if (fp.kobc) go(k_flux<false, 0, true, 15, true>, stage, nullptr, Rout);
+            else go(k_flux<false, 0, true, 15, false>, stage, nullptr, Rout);
+        }
+        return hipGetLastError();
     }
-    if (fp.sqrt_pow == 5) {  // gamma = 1.4
-        if (first) QL_FLUX_LAUNCH(false, 5, true, 3, stage, (const double *)nullptr, Rout);
-        else if (fp.limiter) { QL_FLUX_DISPATCH(true, 5) }
-        else { QL_FLUX_DISPATCH(false, 5) }
-    } else {
-        if (first) QL_FLUX_LAUNCH(false, 0, true, 3, stage, (const double *)nullptr, Rout);
-        else if (fp.limiter) { QL_FLUX_DISPATCH(true, 0) }
-        else { QL_FLUX_DISPATCH(false, 0) }
-    }
-#undef QL_FLUX_DISPATCH
-#undef QL_FLUX_LAUNCH
+    dispatch_flow(fp, [&](auto lim, auto pw, auto kobc) {
+        constexpr bool L = decltype(lim)::value, K = decltype(kobc)::value;
+        constexpr int P = decltype(pw)::value;
+        if (split == 2) {
+            // the s directions, then the n directions with the update
+            go(k_flux<L, P, false, kSPlus | kSMinus, false>, 0, nullptr, Rpart[0]);
+            go(k_flux<L, P, false, kNPlus | kNMinus, K>, stage, Rpart[0], Rout);
+        } else if (split == 4) {
+            // one launch per split stencil, the last with the update
+            go(k_flux<L, P, false, kSPlus, false>, 0, nullptr, Rpart[0]);
+            go(k_flux<L, P, false, kSMinus, false>, 0, Rpart[0], Rpart[1]);
+            go(k_flux<L, P, false, kNPlus, false>, 0, Rpart[1], Rpart[0]);
+            go(k_flux<L, P, false, kNMinus, K>, stage, Rpart[0], Rout);
+        } else {
+            go(k_flux<L, P, false, 15, K>, stage, nullptr, Rout);
+        }
+    });
     return hipGetLastError();
 }
 
@@ -1298,9 +1432,62 @@ __device__ __forceinline__ bool flux_entry_f(uint8_t f, double dx, double dy, do
     return ok;
 }
 
+// FP32 counterpart of mirror_entry; the weight and the sums stay FP64.
+template <bool LIMITER, int POW, bool FIRST>
+__device__ __forceinline__ bool mirror_entry_f(double dx, double dy, double2 N, const float qp[4],
+                                               const float gp[8], const float bp[8],
+                                               const double w[8], const float Ginf[4],
+                                               float gm1inv, float vk, double R[4]) {
+#pragma clang fp contract(off)
+    const double tx = N.y, ty = -N.x;
+    const double ds = fma(dx, tx, dy * ty);
+    const double dm = -fma(dx, N.x, dy * N.y);
+    const float mx = (float)fma(ds, tx, dm * N.x), my = (float)fma(ds, ty, dm * N.y);
+    float qt0[4];
+    if (FIRST) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) qt0[r] = qp[r];
+    } else if (LIMITER) {
+        const float e = vk * __builtin_amdgcn_sqrtf(fmaf(mx, mx, my * my));
+        const float eps2 = fmaxf((e * e) * e, 1e-30f);
+        const float hx = -0.5f * mx, hy = -0.5f * my;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float d0 = fmaf(hx, gp[r], hy * gp[4 + r]);
+            qt0[r] = fmaf(venkat_f(d0, bp[r], bp[4 + r], eps2), d0, qp[r]);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) qt0[r] = fmaf(-0.5f, fmaf(mx, gp[r], my * gp[4 + r]), qp[r]);
+    }
+    PrimF s0;
+    const bool ok = q_to_prim_f<POW>(qt0, gm1inv, s0);
+    float G0[4];
+    split_flux_f(s0, (float)N.x, (float)N.y, -1.0f, G0);
+    const double wm = fma(dm, w[6], -(ds * w[7]));
+#pragma unroll
+    for (int r = 0; r < 4; ++r) R[r] = fma(wm, (double)(Ginf[r] - G0[r]), R[r]);
+    return ok;
+}
+
+// FP32 Gn-(q_inf): q of the conserved freestream in FP64 (as the state's own
+// q and its FP32 shadow are formed), then the FP32 flux path.
+template <int POW>
+__device__ __forceinline__ bool freestream_flux_f(const double *u, double2 N,
+                                                  const FlowParams &fp, float G[4]) {
+    const double v[4] = {u[0], u[1], u[2], u[3]};
+    double qi[4];
+    bool ok = cons_to_q(v, fp, qi) == kErrNone;
+    const float qf[4] = {(float)qi[0], (float)qi[1], (float)qi[2], (float)qi[3]};
+    PrimF si;
+    ok &= q_to_prim_f<POW>(qf, (float)fp.gm1inv, si);
+    split_flux_f(si, (float)N.x, (float)N.y, -1.0f, G);
+    return ok;
+}
+
 }  // namespace
 
-template <bool LIMITER, int POW, bool FIRST>
+template <bool LIMITER, int POW, bool FIRST, bool KOBC>
 // held to 4 waves per SIMD (at most 128 VGPRs), as k_flux is to 3
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 k_flux_mixed(
@@ -1352,7 +1539,7 @@ k_flux_mixed(
     if (j < nown) {
         kd = cl.kind[p];
         const bool frozen = cl.case_active && !cl.case_active[cl.case_of[p]];
-        live = kd != kOuter && !frozen;
+        live = (KOBC || kd != kOuter) && !frozen;
     }
     double2 N = make_double2(0.0, 0.0);
     if (live) {
@@ -1388,7 +1575,10 @@ k_flux_mixed(
         }
 #pragma unroll
         for (int m = 0; m < 8; ++m) w[m] = cl.lsw[8 * p + m];
-        const uint8_t fmask = (kd == kWall) ? uint8_t(~kNPlus) : uint8_t(0xff);
+        uint8_t fmask = (kd == kWall) ? uint8_t(~kNPlus) : uint8_t(0xff);
+        if constexpr (KOBC) {
+            if (kd == kOuter) fmask &= uint8_t(~kNMinus);
+        }
         const int k1 = cl.ptr[p + 1];
         bool ok = true;
 #pragma unroll 2
@@ -1426,6 +1616,18 @@ k_flux_mixed(
             ok &= flux_entry_f<LIMITER, POW, FIRST>(f, Q.x - P.x, Q.y - P.y, N, qi, gi, bi, qp, gp, bp,
                                              w, gm1inv, vk, R);
         }
+        if constexpr (KOBC) {
+            if (kd == kOuter) {
+                float Ginf[4];
+                ok &= freestream_flux_f<POW>(cl.uinf + 4 * cl.case_of[p], N, fp, Ginf);
+                for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
+                    if (!(cl.flag[k] & kNPlus)) continue;
+                    const double2 Q = in_lds ? lxy[cl.flidx[k]] : cl.xy[cl.idx[k]];
+                    ok &= mirror_entry_f<LIMITER, POW, FIRST>(Q.x - P.x, Q.y - P.y, N, qp, gp, bp,
+                                                              w, Ginf, gm1inv, vk, R);
+                }
+            }
+        }
         if (!ok) report(err, p, kErrPositivity);
     }
 #pragma unroll
@@ -1461,19 +1663,16 @@ hipError_t launch_flux_mixed(hipStream_t st, const DevCloud &c, const FlowParams
     const int cap = lds_cap(c, lds_budget, rec);
     const size_t shmem = (size_t)cap * rec;
     const dim3 grid(num_flux_tiles(c.n)), block(kBlock);
-#define QL_FLUXM_LAUNCH(LIM, POW, FIRST)                                                     \
-    hipLaunchKernelGGL((k_flux_mixed<LIM, POW, FIRST>), grid, block, shmem, st, c, fp, stage, \
-                       cap, q, q32, g32, qmm32, U, Un, dt, qnext, q32next, Rout, err)
-    if (fp.sqrt_pow == 5) {
-        if (first) QL_FLUXM_LAUNCH(false, 5, true);
-        else if (fp.limiter) QL_FLUXM_LAUNCH(true, 5, false);
-        else QL_FLUXM_LAUNCH(false, 5, false);
-    } else {
-        if (first) QL_FLUXM_LAUNCH(false, 0, true);
-        else if (fp.limiter) QL_FLUXM_LAUNCH(true, 0, false);
-        else QL_FLUXM_LAUNCH(false, 0, false);
-    }
-#undef QL_FLUXM_LAUNCH
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, block, shmem, st, c, fp, stage, cap, q, q32, g32, qmm32, U,
+                           Un, dt, qnext, q32next, Rout, err);
+    };
+    dispatch_flow(fp, [&](auto lim, auto pw, auto kobc) {
+        constexpr bool L = decltype(lim)::value, K = decltype(kobc)::value;
+        constexpr int P = decltype(pw)::value;
+        if (first) go(k_flux_mixed<false, P, true, K>);  // the limiter is unused
+        else go(k_flux_mixed<L, P, false, K>);
+    });
     return hipGetLastError();
 }
 
@@ -1482,7 +1681,8 @@ hipError_t launch_flux_mixed(hipStream_t st, const DevCloud &c, const FlowParams
 // workgroup sums R_c^2 over a chunk, then one workgroup adds each case's
 // chunk sums and writes sqrt(sum / updated points) into history row
 // (*ctr) and advances *ctr (replays of a captured iteration need no host
-// bookkeeping).  Outer and frozen points carry R = 0.
+// bookkeeping).  Held (outer without the kinetic outer condition) and
+// frozen points carry R = 0.
 __global__ void __launch_bounds__(kBlock) k_res_chunks(const double *__restrict__ R, int n,
                                                        const int *__restrict__ beg,
                                                        double *__restrict__ part) {

@@ -61,6 +61,7 @@ struct ql_solver {
     int ncase = 0;
     std::vector<int> case_lo;        // [ncase+1] first point of each case
     std::vector<int> case_nupd;      // updated (interior + wall) points per case
+    int outer_bad = -1;  // first outer point (caller order) with a singular split stencil
     std::vector<int> wall_lo;        // [ncase+1] offsets into the wall list
     std::vector<double> case_mach, case_alpha;
     bool has_cloud = false, has_state = false, has_eval = false, has_res = false;
@@ -77,7 +78,7 @@ struct ql_solver {
     double2 *q[2] = {nullptr, nullptr}, *g[3] = {nullptr, nullptr, nullptr}, *qmm = nullptr;
     float4 *q32[2] = {nullptr, nullptr}, *g32 = nullptr, *qmm32 = nullptr;  // FP32 shadows
     double *lsi = nullptr;
-    double *Rpart = nullptr;  // [4][n], the s-direction part of a split flux sweep
+    double *Rpart[2] = {nullptr, nullptr};  // [4][n] partial sums of a split flux sweep
     int *fhalo_ptr = nullptr, *fhalo_idx = nullptr;  // tiles of kFluxTile points
     uint16_t *flidx = nullptr;
     int fmax_slots = 0;
@@ -88,11 +89,14 @@ struct ql_solver {
     uint8_t *wsel = nullptr;                    // warm start: per-case choice
     double *wres = nullptr;                     // warm start: [2][ncase][4] residual norms
     uint8_t *case_active = nullptr, *tile_active = nullptr;
+    // inv_nupd: [2][ncase] 1 / (points in the residual norm): interior and
+    // wall points; all points (kinetic outer condition)
     double *uinf = nullptr, *part = nullptr, *inv_nupd = nullptr;
     int nchunk = 0;
     int zero = 0;  // source of the history-row counter reset
     int reshist_cap = 0;
     int *errw = nullptr;
+    int *errw_outer = nullptr;  // singular split stencils of outer points (set-up)
     int err_init[2] = {INT_MAX, 0};  // source of the error-word reset copies
     int qcur = 0, gfin = 0;
     std::vector<double> last_res;  // [ncase][4]
@@ -150,7 +154,8 @@ void free_cloud(ql_solver *s) {
     dfree(s->dperm); dfree(s->wall); dfree(s->lsw); dfree(s->dmin); dfree(s->U); dfree(s->Un);
     dfree(s->dt); dfree(s->R); dfree(s->tmp); dfree(s->q[0]); dfree(s->q[1]); dfree(s->g[0]);
     dfree(s->g[1]); dfree(s->g[2]); dfree(s->qmm); dfree(s->reshist);
-    dfree(s->fscratch); dfree(s->fout); dfree(s->errw); dfree(s->lsi); dfree(s->Rpart);
+    dfree(s->fscratch); dfree(s->fout); dfree(s->errw); dfree(s->lsi); dfree(s->Rpart[0]);
+    dfree(s->Rpart[1]); dfree(s->errw_outer);
     dfree(s->fhalo_ptr); dfree(s->fhalo_idx); dfree(s->flidx);
     dfree(s->q32[0]); dfree(s->q32[1]); dfree(s->g32); dfree(s->qmm32);
     dfree(s->case_of); dfree(s->chunk_beg); dfree(s->chunk_ptr); dfree(s->ctr);
@@ -347,6 +352,7 @@ DevCloud dev_cloud(const ql_solver *s) {
     c.case_of = s->case_of;
     c.case_active = s->case_active;
     c.tile_active = s->tile_active;
+    c.uinf = s->uinf;
     return c;
 }
 
@@ -359,6 +365,7 @@ FlowParams flow_params(const ql_solver *s) {
     f.n_inner = s->prm.n_inner;
     f.limiter = s->prm.limiter;
     f.order = s->prm.order;
+    f.kobc = s->prm.outer_bc;
     const double m = 2.0 / (s->prm.gamma - 1.0);
     const double mr = std::nearbyint(m);
     f.sqrt_pow = (std::fabs(m - mr) <= 1e-12 * m && mr >= 1.0 && mr <= 16.0) ? (int)mr : 0;
@@ -382,8 +389,13 @@ int check_params(ql_solver *s, const ql_params *p) {
     if (p->grad_lds < 0 || p->grad_lds > 160 * 1024)
         return fail(s, QL_EINVAL, "grad_lds must lie in [0, 163840] bytes");
     if (p->order != 1 && p->order != 2) return fail(s, QL_EINVAL, "order must be 1 or 2");
-    if (p->flux_split != 0 && p->flux_split != 1)
-        return fail(s, QL_EINVAL, "flux_split must be 0 or 1");
+    if (p->flux_split < 0 || p->flux_split > 2)
+        return fail(s, QL_EINVAL, "flux_split must be 0, 1 or 2");
+    if (p->outer_bc != 0 && p->outer_bc != 1) return fail(s, QL_EINVAL, "outer_bc must be 0 or 1");
+    if (p->outer_bc == 1 && s->has_cloud && s->outer_bad >= 0)
+        return fail(s, QL_ESINGULAR,
+                    "kinetic outer condition: singular split stencil at outer point %d",
+                    s->outer_bad);
     return QL_OK;
 }
 
@@ -552,7 +564,7 @@ int launch_stage(ql_solver *s, const DevCloud &c, const FlowParams &fp, int stag
     else
         HIPCHK(s, launch_flux(s->stream, c, fp, stage, lds, s->q[a], s->g[s->gfin], s->qmm, s->U,
                               s->Un, s->dt, s->q[b], Rout, s->q32[b], s->errw,
-                              (s->prm.flux_split && fp.order == 2) ? s->Rpart : nullptr));
+                              fp.order == 2 ? 2 * s->prm.flux_split : 0, s->Rpart));
     return QL_OK;
 }
 
@@ -571,7 +583,8 @@ int enqueue_iteration(ql_solver *s, const DevCloud &c, const FlowParams &fp, int
     }
     Timer t(s, 3);
     HIPCHK(s, launch_resnorm(s->stream, s->R, s->n, s->nchunk, s->chunk_beg, s->part, s->ncase,
-                             s->chunk_ptr, s->inv_nupd, s->ctr, hist_cap, s->reshist));
+                             s->chunk_ptr, s->inv_nupd + (fp.kobc ? s->ncase : 0), s->ctr,
+                             hist_cap, s->reshist));
     t.done();
     return QL_OK;
 }
@@ -655,6 +668,7 @@ void ql_default_params(ql_params *p) {
     p->grad_lds = 0;
     p->order = 2;
     p->flux_split = 0;
+    p->outer_bc = 0;
 }
 
 int ql_create(ql_solver **out, int32_t device, void *hip_stream) {
@@ -711,7 +725,9 @@ int ql_set_params(ql_solver *s, const ql_params *p) {
     if (st) return st;
     s->prm = *p;
     drop_graph(s);
-    if (s->has_cloud && p->flux_split && !s->Rpart) HIPCHK(s, dalloc(&s->Rpart, (size_t)4 * s->n));
+    for (int k = 0; k < 2; ++k)
+        if (s->has_cloud && p->flux_split && !s->Rpart[k])
+            HIPCHK(s, dalloc(&s->Rpart[k], (size_t)4 * s->n));
     return QL_OK;
 }
 
@@ -802,7 +818,7 @@ static int upload_impl(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int
     // the residual reduction (never straddling a case)
     constexpr int kChunk = 4096;
     std::vector<int> hwall, wall_lo(ncase + 1, 0), nupd(ncase, 0), cbeg, cptr(ncase + 1, 0);
-    std::vector<double> inv_nupd(ncase);
+    std::vector<double> inv_nupd(2 * (size_t)ncase);
     for (int c = 0; c < ncase; ++c) {
         const int lo = (int)case_ptr[c], hi = (int)case_ptr[c + 1];
         for (int p = lo; p < hi; ++p) {
@@ -811,6 +827,7 @@ static int upload_impl(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int
         }
         wall_lo[c + 1] = (int)hwall.size();
         inv_nupd[c] = nupd[c] > 0 ? 1.0 / nupd[c] : 0.0;
+        inv_nupd[ncase + c] = 1.0 / (hi - lo);
         for (int b = lo; b < hi; b += kChunk) cbeg.push_back(b);
         cptr[c + 1] = (int)cbeg.size();
     }
@@ -837,7 +854,7 @@ static int upload_impl(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int
     HIPCHK(s, dalloc(&s->dperm, n)); HIPCHK(s, dalloc(&s->wall, hwall.size()));
     HIPCHK(s, dalloc(&s->lsw, (size_t)8 * n)); HIPCHK(s, dalloc(&s->dmin, n));
     HIPCHK(s, dalloc(&s->lsi, (size_t)3 * n));
-    if (s->prm.flux_split) HIPCHK(s, dalloc(&s->Rpart, (size_t)4 * n));
+    for (int k = 0; k < 2 && s->prm.flux_split; ++k) HIPCHK(s, dalloc(&s->Rpart[k], (size_t)4 * n));
     HIPCHK(s, dalloc(&s->U, (size_t)4 * n)); HIPCHK(s, dalloc(&s->Un, (size_t)4 * n));
     HIPCHK(s, dalloc(&s->dt, n)); HIPCHK(s, dalloc(&s->R, (size_t)4 * n));
     HIPCHK(s, dalloc(&s->tmp, (size_t)4 * n));
@@ -849,10 +866,11 @@ static int upload_impl(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int
     HIPCHK(s, dalloc(&s->g32, (size_t)2 * n)); HIPCHK(s, dalloc(&s->qmm32, (size_t)2 * n));
     HIPCHK(s, dalloc(&s->fscratch, (size_t)3 * std::max<size_t>(hwall.size(), 1)));
     HIPCHK(s, dalloc(&s->fout, 2)); HIPCHK(s, dalloc(&s->errw, 2));
+    HIPCHK(s, dalloc(&s->errw_outer, 2));
     HIPCHK(s, dalloc(&s->case_of, n)); HIPCHK(s, dalloc(&s->uinf, (size_t)4 * ncase));
     HIPCHK(s, dalloc(&s->case_active, ncase)); HIPCHK(s, dalloc(&s->tile_active, ntile));
     HIPCHK(s, dalloc(&s->chunk_beg, nchunk + 1)); HIPCHK(s, dalloc(&s->chunk_ptr, ncase + 1));
-    HIPCHK(s, dalloc(&s->part, (size_t)4 * nchunk)); HIPCHK(s, dalloc(&s->inv_nupd, ncase));
+    HIPCHK(s, dalloc(&s->part, (size_t)4 * nchunk)); HIPCHK(s, dalloc(&s->inv_nupd, 2 * ncase));
     HIPCHK(s, dalloc(&s->ctr, 1));
     HIPCHK(s, dalloc(&s->dwall_lo, ncase + 1)); HIPCHK(s, dalloc(&s->wctr, 1));
     HIPCHK(s, dalloc(&s->wsel, ncase)); HIPCHK(s, dalloc(&s->wres, (size_t)8 * ncase));
@@ -875,7 +893,8 @@ static int upload_impl(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int
     HIPCHK(s, hipMemcpyAsync(s->tile_active, ones_t.data(), ntile, hipMemcpyHostToDevice, st));
     HIPCHK(s, hipMemcpyAsync(s->chunk_beg, cbeg.data(), sizeof(int) * (nchunk + 1), hipMemcpyHostToDevice, st));
     HIPCHK(s, hipMemcpyAsync(s->chunk_ptr, cptr.data(), sizeof(int) * (ncase + 1), hipMemcpyHostToDevice, st));
-    HIPCHK(s, hipMemcpyAsync(s->inv_nupd, inv_nupd.data(), sizeof(double) * ncase, hipMemcpyHostToDevice, st));
+    HIPCHK(s, hipMemcpyAsync(s->inv_nupd, inv_nupd.data(), sizeof(double) * inv_nupd.size(),
+                             hipMemcpyHostToDevice, st));
     {
         std::vector<int> thptr, thidx;
         std::vector<uint16_t> tlidx;
@@ -904,10 +923,19 @@ static int upload_impl(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int
 
     int rc = reset_err(s);
     if (rc) return rc;
+    HIPCHK(s, hipMemcpyAsync(s->errw_outer, s->err_init, sizeof s->err_init,
+                             hipMemcpyHostToDevice, st));
     HIPCHK(s, launch_setup(st, n, s->xy, s->nrm, s->kind, s->ptr, s->idx, s->flag,
-                           nbr_flag ? 0 : 1, s->lsw, s->lsi, s->dmin, s->errw));
+                           nbr_flag ? 0 : 1, s->lsw, s->lsi, s->dmin, s->errw, s->errw_outer));
+    int eo[2] = {INT_MAX, 0};
+    HIPCHK(s, hipMemcpyAsync(eo, s->errw_outer, sizeof eo, hipMemcpyDeviceToHost, st));
     // host buffers above must outlive the asynchronous copies
     rc = sync_and_check(s, "upload");
+    s->outer_bad = (eo[1] != kErrNone && eo[0] >= 0 && eo[0] < n) ? s->perm[eo[0]] : -1;
+    if (!rc && s->prm.outer_bc == 1 && s->outer_bad >= 0)
+        rc = fail(s, QL_ESINGULAR,
+                  "upload: kinetic outer condition: singular split stencil at outer point %d",
+                  s->outer_bad);
     if (rc) {
         const std::string msg = s->err;
         free_cloud(s);
@@ -1177,7 +1205,8 @@ static int warm_eval(ql_solver *s, const DevCloud &c, const FlowParams &fp) {
     if ((st = run_gradients(s, c, fp.limiter != 0, false))) return st;
     if ((st = launch_stage(s, c, fp, 0, s->R))) return st;
     HIPCHK(s, launch_resnorm(s->stream, s->R, s->n, s->nchunk, s->chunk_beg, s->part, s->ncase,
-                             s->chunk_ptr, s->inv_nupd, s->wctr, 2, s->wres));
+                             s->chunk_ptr, s->inv_nupd + (fp.kobc ? s->ncase : 0), s->wctr, 2,
+                             s->wres));
     return QL_OK;
 }
 

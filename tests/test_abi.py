@@ -26,8 +26,8 @@ def test_host_side_checks_without_gpu():
     from paper_2108_07031_amd import qlskum as q
     p = q.ql_default_params()
     assert (p.gamma, p.mach, p.alpha_deg, p.cfl, p.n_inner, p.limiter) == (1.4, 0.63, 2.0, 0.2, 3, 0)
-    assert (p.precision, p.reorder, p.flux_lds, p.grad_lds, p.order, p.flux_split) == \
-        (0, 1, 0, 0, 2, 0)
+    assert (p.precision, p.reorder, p.flux_lds, p.grad_lds, p.order, p.flux_split,
+            p.outer_bc) == (0, 1, 0, 0, 2, 0, 0)
     h = C.c_void_p()
     assert q.lib.ql_create(None, 0, None) == q.QL_EINVAL
     rc = q.lib.ql_create(C.byref(h), -1, None)
@@ -37,10 +37,23 @@ def test_host_side_checks_without_gpu():
     assert q.lib.ql_residual_norm(None, out) == q.QL_EINVAL
 
 
-def test_params_struct_layout():
+def test_params_struct_layout(tmp_path):
+    """The binding's ql_params matches the C compiler's layout of the header's
+    struct field by field (offsets and size)."""
+    import subprocess
     from paper_2108_07031_amd import qlskum as q
-    # doubles and int32s as in the header: 4 d, 2 i32, 1 d, 6 i32
-    assert C.sizeof(q.ql_params) == 4 * 8 + 2 * 4 + 8 + 6 * 4
-    assert q.ql_params.order.offset == 4 * 8 + 2 * 4 + 8 + 4 * 4
-    assert q.ql_params.flux_lds.offset == 4 * 8 + 2 * 4 + 8 + 2 * 4
-    assert q.ql_params.grad_lds.offset == 4 * 8 + 2 * 4 + 8 + 3 * 4
+    fields = [f for f, _ in q.ql_params._fields_]
+    prog = tmp_path / "layout.c"
+    body = "".join(f'    printf("%s %zu\\n", "{f}", offsetof(ql_params, {f}));\n' for f in fields)
+    prog.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "qlskum.h"\n'
+                    'int main(void) {\n' + body +
+                    '    printf("sizeof %zu\\n", sizeof(ql_params));\n    return 0;\n}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o",
+                    str(exe)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True,
+                                                        text=True, check=True).stdout.split("\n")
+               if line)
+    for f in fields:
+        assert int(out[f]) == getattr(q.ql_params, f).offset, f
+    assert int(out["sizeof"]) == C.sizeof(q.ql_params)

@@ -1,0 +1,167 @@
+"""GPU parity of the kinetic outer boundary condition (params outer_bc = 1).
+
+The paper (sec. 2.1) combines the defect-corrected scheme with a kinetic
+outer boundary condition whose formula it leaves to a reference.  Reading
+(the oracle's, pinned on the CPU in test_oracle_pins_kobc.py): an outer
+point's n- split stencil, which would lie beyond the far field, is replaced
+by the mirror image of its n+ stencil through the point's tangent line,
+whose points hold the freestream Maxwellian; outer points are then updated
+and counted in the residual norm.
+
+Tolerances as in test_gpu_parity.py: one evaluation 5e-12 normwise per
+residual component (outer points included), 100 iterations 1e-11 per state
+component, residual history 1e-10; mixed precision 2e-3 for one evaluation.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from cloudgen import KIND_OUTER
+from tests._common import cloud, normwise_rel, smooth_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ql():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2108_07031_amd import qlskum
+    return qlskum
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("limiter", [0, 1])
+def test_freestream_preserved(ql, limiter, precision):
+    """The raw freestream (no wall projection) gives R = 0 bit for bit at
+    every point, the outer points' mirrored term included."""
+    _say(f"kobc freestream limiter={limiter} precision={precision}")
+    c = cloud("jitter")
+    prm = dict(limiter=limiter, precision=precision, outer_bc=1, mach=0.7, alpha_deg=3.0)
+    o = oracle.Oracle(c, oracle.params(limiter=limiter, outer_bc=1, mach=0.7, alpha_deg=3.0))
+    s = ql.Solver(c, **prm)
+    s.set_state(o.freestream(project_wall=False))
+    assert np.count_nonzero(s.evaluate()["R"]) == 0
+    s.close()
+
+
+@pytest.mark.parametrize("limiter", [0, 1])
+@pytest.mark.parametrize("name", ["c1", "jitter"])
+def test_evaluate_parity(ql, name, limiter):
+    _say(f"kobc evaluate {name} limiter={limiter}")
+    c = cloud(name)
+    prm = dict(limiter=limiter, mach=0.85 if limiter else 0.63, alpha_deg=1.0 if limiter else 2.0,
+               outer_bc=1)
+    o = oracle.Oracle(c, oracle.params(**prm))
+    s = ql.Solver(c, **prm)
+    # a state away from the freestream at the outer layer as well
+    U = smooth_state(c, mach=prm["mach"], alpha_deg=prm["alpha_deg"])
+    s.set_state(U)
+    gpu = s.evaluate()
+    ora = o.evaluate(U)
+    outer = c.kind == KIND_OUTER
+    assert np.abs(ora["R"][:, outer]).max() > 0  # the outer points carry a residual
+    assert np.all(normwise_rel(gpu["R"], ora["R"]) <= 5e-12)
+    assert np.all(normwise_rel(gpu["R"][:, outer], ora["R"][:, outer]) <= 5e-12)
+    s.close()
+
+
+@pytest.mark.parametrize("limiter", [0, 1])
+def test_run_parity_c1_100(ql, limiter):
+    """160 x 60 cloud from the freestream: 100 iterations with the kinetic
+    outer condition against the oracle (state, residual history, forces)."""
+    _say(f"kobc run c1 100 limiter={limiter}")
+    c = cloud("c1")
+    prm = dict(limiter=limiter, outer_bc=1)
+    o = oracle.Oracle(c, oracle.params(**prm))
+    s = ql.Solver(c, **prm)
+    s.init_freestream()
+    hist_g = s.step(100)
+    Ug = s.fetch_state()
+    Uo, hist_o = o.run(o.freestream(), 100)
+    err = normwise_rel(Ug, Uo)
+    _say(f"  state err {err}")
+    assert np.all(err <= 1e-11), err
+    outer = c.kind == KIND_OUTER
+    # the outer layer moved away from the freestream
+    assert np.abs(Uo[:, outer] - o.freestream()[:, outer]).max() > 1e-8
+    assert np.all(normwise_rel(hist_g.T, hist_o.T) <= 1e-10)
+    clg, cdg = s.forces()
+    clo, cdo = o.forces(Uo)
+    assert abs(clg - clo) <= 1e-10 * max(1.0, abs(clo))
+    assert abs(cdg - cdo) <= 1e-10 * max(1.0, abs(cdo))
+    s.close()
+
+
+@pytest.mark.parametrize("limiter", [0, 1])
+def test_mixed_evaluate(ql, limiter):
+    """Mixed precision with the kinetic outer condition: one evaluation
+    within the FP32 flux body's bound of the oracle, outer points included."""
+    _say(f"kobc mixed evaluate limiter={limiter}")
+    c = cloud("jitter")
+    prm = dict(limiter=limiter, mach=0.85 if limiter else 0.63, alpha_deg=1.0 if limiter else 2.0,
+               outer_bc=1)
+    o = oracle.Oracle(c, oracle.params(**prm))
+    s = ql.Solver(c, precision=1, **prm)
+    U = smooth_state(c, mach=prm["mach"], alpha_deg=prm["alpha_deg"])
+    s.set_state(U)
+    R = s.evaluate()["R"]
+    assert np.all(normwise_rel(R, o.evaluate(U)["R"]) <= 2e-3)
+    s.close()
+
+
+def test_split_sweeps_with_kinetic_outer(ql):
+    """The two- and four-launch flux sweeps with the kinetic outer condition
+    agree with the fused sweep (summation grouping only) and the oracle."""
+    _say("kobc split sweeps")
+    c = cloud("jitter")
+    prm = dict(limiter=1, mach=0.85, alpha_deg=1.0, outer_bc=1)
+    U = smooth_state(c, mach=0.85, alpha_deg=1.0)
+    ora = oracle.Oracle(c, oracle.params(**prm)).evaluate(U)["R"]
+    R = {}
+    for split in (0, 1, 2):
+        s = ql.Solver(c, flux_split=split, **prm)
+        s.set_state(U)
+        R[split] = s.evaluate()["R"]
+        s.close()
+    for split in (1, 2):
+        assert np.all(normwise_rel(R[split], R[0]) <= 1e-13), split
+        assert np.all(normwise_rel(R[split], ora) <= 5e-12), split
+
+
+def test_singular_outer_stencil_rejected(ql):
+    """An outer point whose s+ stencil has a single point: the cloud uploads
+    with the outer points held, and switching the kinetic outer condition on
+    fails with QL_ESINGULAR naming that point; the solver stays usable."""
+    _say("kobc singular outer stencil")
+    from cloudgen import Cloud
+    c = cloud("small")
+    o = oracle.Oracle(c)
+    p = int(np.flatnonzero(c.kind == KIND_OUTER)[5])
+    ks = np.arange(c.nbr_ptr[p], c.nbr_ptr[p + 1])
+    fl = o.flag[ks]
+    # keep one s+ member and every entry outside s+ (n+ and s- members)
+    keep = np.concatenate([ks[fl & oracle.S_PLUS != 0][:1], ks[fl & oracle.S_PLUS == 0]])
+    keep.sort()
+    lists = [c.nbr_idx[c.nbr_ptr[i]:c.nbr_ptr[i + 1]] if i != p else c.nbr_idx[keep]
+             for i in range(c.n)]
+    ptr = np.zeros(c.n + 1, np.int32)
+    np.cumsum([len(v) for v in lists], out=ptr[1:])
+    bad = Cloud(x=c.x, y=c.y, nx=c.nx, ny=c.ny, kind=c.kind, nbr_ptr=ptr,
+                nbr_idx=np.concatenate(lists).astype(np.int32))
+    s = ql.Solver(bad)
+    with pytest.raises(ql.QLError) as e:
+        s.set_params(outer_bc=1)
+    assert e.value.code == ql.QL_ESINGULAR and f"point {p}" in str(e.value)
+    s.set_params(outer_bc=0)
+    s.init_freestream()
+    s.step(2)
+    s.close()
+    with pytest.raises(ql.QLError) as e:
+        ql.Solver(bad, outer_bc=1)
+    assert e.value.code == ql.QL_ESINGULAR and f"point {p}" in str(e.value)

@@ -442,17 +442,17 @@ def test_first_order_parity(ql, precision):
 
 @pytest.mark.parametrize("limiter", [0, 1])
 def test_split_flux_sweep(ql, limiter):
-    """flux_split = 1 (s directions and n directions in two launches) gives
-    the fused sweep's residual up to the summation grouping (1e-13) and the
-    oracle's within the evaluation bound (5e-12); 20 iterations stay within
-    1e-12 of the fused run."""
+    """flux_split = 1 (s directions and n directions in two launches) and 2
+    (one launch per split stencil) give the fused sweep's residual up to the
+    summation grouping (1e-13) and the oracle's within the evaluation bound
+    (5e-12); 20 iterations stay within 1e-12 of the fused run."""
     _say(f"split flux sweep limiter={limiter}")
     c = cloud("jitter")
     prm = dict(limiter=limiter, mach=0.85 if limiter else 0.63, alpha_deg=1.0 if limiter else 2.0)
     U = smooth_state(c, mach=prm["mach"], alpha_deg=prm["alpha_deg"])
     ora = oracle.Oracle(c, oracle.params(**prm)).evaluate(U)
     out = {}
-    for split in (0, 1):
+    for split in (0, 1, 2):
         s = ql.Solver(c, flux_split=split, **prm)
         s.set_state(U)
         R = s.evaluate()["R"]
@@ -460,6 +460,7 @@ def test_split_flux_sweep(ql, limiter):
         s.step(20)
         out[split] = (R, s.fetch_state())
         s.close()
-    assert np.all(normwise_rel(out[1][0], out[0][0]) <= 1e-13)
-    assert np.all(normwise_rel(out[1][0], ora["R"]) <= 5e-12)
-    assert np.all(normwise_rel(out[1][1], out[0][1]) <= 1e-12)
+    for split in (1, 2):
+        assert np.all(normwise_rel(out[split][0], out[0][0]) <= 1e-13), split
+        assert np.all(normwise_rel(out[split][0], ora["R"]) <= 5e-12), split
+        assert np.all(normwise_rel(out[split][1], out[0][1]) <= 1e-12), split
