@@ -38,6 +38,16 @@ def build_fma():
     return build(cflags=("-O2", "-mfma", "-ffp-contract=fast"), out=FMA_LIB)
 
 
+OMP_LIB = os.path.join(_HERE, "liboracle_omp.so")
+
+
+def build_omp():
+    """The same source with OpenMP: the loops over points run on every host
+    core (OMP_NUM_THREADS), with results bit for bit those of the serial
+    build.  Used only to time the CPU baseline."""
+    return build(cflags=("-O2", "-ffp-contract=off", "-fopenmp"), out=OMP_LIB)
+
+
 class OracleError(RuntimeError):
     def __init__(self, code, point):
         super().__init__(f"oracle status {code} at point {point}")
@@ -75,11 +85,15 @@ def load(path=_LIB):
             build()
         elif path == FMA_LIB:
             build_fma()
+        elif path == OMP_LIB:
+            build_omp()
         else:
             raise FileNotFoundError(path)
     lib = C.CDLL(path)
     vp, i64, i32, d = C.c_void_p, C.c_int64, C.c_int32, C.c_double
     P = C.POINTER
+    lib.ora_num_threads.argtypes = []
+    lib.ora_num_threads.restype = C.c_int
     lib.ora_classify.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, P(i64)]
     lib.ora_q_variables.argtypes = [i64, vp, d, vp, P(i64)]
     lib.ora_q_derivatives.argtypes = [P(_Cloud), i32, vp, vp, vp, vp]

@@ -6,7 +6,11 @@
  * no code with it.  It is written to be read against the paper: single
  * thread, caller's point order and neighbour order, every sum in the order
  * the formulas state it, libm transcendentals, compiled without FMA
- * contraction.
+ * contraction.  A second build of this same source with OpenMP (used only
+ * to time the CPU baseline on every host core) runs the loops over points
+ * in parallel: each point's arithmetic and the order of every sum over
+ * points are unchanged, so its results are the serial build's bit for bit;
+ * a failing step reports the smallest failing point in both builds.
  *
  * Paper: "On the performance of GPU accelerated q-LSKUM based meshfree
  * solvers in Fortran, C++, Python, and Julia" (Scientific Computing Report
@@ -32,6 +36,33 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* threads the loops over points use (1 in the serial build) */
+int ora_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* keep (point, status) of the smallest failing point */
+static void note_failure(int64_t p, int st, int64_t *bad, int *code)
+{
+#ifdef _OPENMP
+#pragma omp critical(ora_failure)
+#endif
+    {
+        if (p < *bad) {
+            *bad = p;
+            *code = st;
+        }
+    }
+}
 
 #define ORA_OK 0
 #define ORA_EINVAL (-1)
@@ -257,6 +288,7 @@ void ora_freestream(int64_t n, const double *nx, const double *ny, const uint8_t
 void ora_timestep(const ora_cloud *cl, const ora_params *prm, const double *U, double *dt)
 {
     int64_t n = cl->n;
+#pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < n; ++p) {
         double dmin = INFINITY;
         for (int32_t k = cl->ptr[p]; k < cl->ptr[p + 1]; ++k) {
@@ -277,19 +309,29 @@ void ora_timestep(const ora_cloud *cl, const ora_params *prm, const double *U, d
 /* Algorithm 1, q_variables(): eq. (26) at every point.                 */
 /* ------------------------------------------------------------------ */
 
+static int q_variables_point(int64_t n, const double *U, double gamma, double *q, int64_t p)
+{
+    double Up[4] = {U[p], U[n + p], U[2 * n + p], U[3 * n + p]}, prim[4], qp[4];
+    for (int c = 0; c < 4; ++c)
+        if (!isfinite(Up[c])) return ORA_ENONFINITE;
+    ora_u_to_prim(Up, gamma, prim);
+    if (!(prim[0] > 0.0) || !(prim[3] > 0.0)) return ORA_EPOSITIVITY;
+    ora_prim_to_q(prim, gamma, qp);
+    for (int c = 0; c < 4; ++c) q[c * n + p] = qp[c];
+    return ORA_OK;
+}
+
 int ora_q_variables(int64_t n, const double *U, double gamma, double *q, int64_t *bad_point)
 {
-    *bad_point = -1;
+    int64_t bad = INT64_MAX;
+    int code = ORA_OK;
+#pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < n; ++p) {
-        double Up[4] = {U[p], U[n + p], U[2 * n + p], U[3 * n + p]}, prim[4], qp[4];
-        for (int c = 0; c < 4; ++c)
-            if (!isfinite(Up[c])) { *bad_point = p; return ORA_ENONFINITE; }
-        ora_u_to_prim(Up, gamma, prim);
-        if (!(prim[0] > 0.0) || !(prim[3] > 0.0)) { *bad_point = p; return ORA_EPOSITIVITY; }
-        ora_prim_to_q(prim, gamma, qp);
-        for (int c = 0; c < 4; ++c) q[c * n + p] = qp[c];
+        int st = q_variables_point(n, U, gamma, q, p);
+        if (st) note_failure(p, st, &bad, &code);
     }
-    return ORA_OK;
+    *bad_point = (code != ORA_OK) ? bad : -1;
+    return code;
 }
 
 /* ------------------------------------------------------------------ */
@@ -318,6 +360,7 @@ void ora_q_derivatives(const ora_cloud *cl, int32_t n_inner, const double *q, do
 {
     int64_t n = cl->n;
     double *gprev = (double *)malloc(sizeof(double) * 8 * (size_t)n);
+#pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < n; ++p) {
         double a = 0, b = 0, c = 0, sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
         double mx[4], mn[4];
@@ -347,6 +390,7 @@ void ora_q_derivatives(const ora_cloud *cl, int32_t n_inner, const double *q, do
     }
     for (int32_t it = 0; it < n_inner; ++it) {
         memcpy(gprev, g, sizeof(double) * 8 * (size_t)n);
+#pragma omp parallel for schedule(static)
         for (int64_t p = 0; p < n; ++p) {
             double a = 0, b = 0, c = 0, sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
             for (int32_t k = cl->ptr[p]; k < cl->ptr[p + 1]; ++k) {
@@ -466,13 +510,109 @@ typedef struct {
     double ss, sn, nn, sG[4], nG[4];
 } bucket;
 
+/* the residual of point p (all four components into R); ORA_EPOSITIVITY
+ * when a modified state has no Maxwellian */
+static int flux_point(const ora_cloud *cl, const ora_params *prm, const double *q,
+                      const double *g, const double *qmax, const double *qmin,
+                      const double prinf[4], int64_t p, double *R)
+{
+    int64_t n = cl->n;
+    double gamma = prm->gamma;
+    int kobc = prm->outer_bc == 1;
+    for (int r = 0; r < 4; ++r) R[r * n + p] = 0.0;
+    if (cl->kind[p] == KIND_OUTER && !kobc) return ORA_OK;
+    double nx = cl->nx[p], ny = cl->ny[p];
+    double tx = ny, ty = -nx;
+    bucket bk[4];
+    memset(bk, 0, sizeof bk);
+    for (int32_t k = cl->ptr[p]; k < cl->ptr[p + 1]; ++k) {
+        int32_t i = cl->idx[k];
+        uint8_t f = cl->flag[k];
+        if (cl->kind[p] == KIND_WALL) f &= (uint8_t)~SPLIT_N_PLUS;
+        if (cl->kind[p] == KIND_OUTER) f &= (uint8_t)~SPLIT_N_MINUS;
+        if (f == 0) continue;
+        double dx = cl->x[i] - cl->x[p], dy = cl->y[i] - cl->y[p];
+        double ds = dx * tx + dy * ty;
+        double dn = dx * nx + dy * ny;
+        double qti[4], qt0[4];
+        ora_modified_q(cl, prm, q, g, qmax, qmin, p, k, qti, qt0);
+        if (!(qti[3] < 0.0) || !(qt0[3] < 0.0)) return ORA_EPOSITIVITY;
+        double pri[4], pr0[4];
+        ora_q_to_prim(qti, gamma, pri);
+        ora_q_to_prim(qt0, gamma, pr0);
+        for (int r = 0; r < 4; ++r)
+            if (!isfinite(pri[r]) || !isfinite(pr0[r])) return ORA_EPOSITIVITY;
+        for (int dir = 0; dir < 2; ++dir) {
+            uint8_t fp = dir ? SPLIT_N_PLUS : SPLIT_S_PLUS;
+            uint8_t fm = dir ? SPLIT_N_MINUS : SPLIT_S_MINUS;
+            int sign, b;
+            if (f & fp) { sign = 1; b = 2 * dir; }
+            else if (f & fm) { sign = -1; b = 2 * dir + 1; }
+            else continue;
+            double ex = dir ? nx : tx, ey = dir ? ny : ty;
+            double Gi[4], G0[4];
+            ora_split_flux(pri, ex, ey, sign, gamma, Gi);
+            ora_split_flux(pr0, ex, ey, sign, gamma, G0);
+            bk[b].ss += ds * ds;
+            bk[b].sn += ds * dn;
+            bk[b].nn += dn * dn;
+            for (int r = 0; r < 4; ++r) {
+                double dG = Gi[r] - G0[r];
+                bk[b].sG[r] += ds * dG;
+                bk[b].nG[r] += dn * dG;
+            }
+        }
+    }
+    if (cl->kind[p] == KIND_OUTER) {
+        /* the mirrored n+ stencil at the freestream replaces n- */
+        memset(&bk[3], 0, sizeof bk[3]);
+        double Ginf[4];
+        ora_split_flux(prinf, nx, ny, -1, gamma, Ginf);
+        for (int32_t k = cl->ptr[p]; k < cl->ptr[p + 1]; ++k) {
+            if (!(cl->flag[k] & SPLIT_N_PLUS)) continue;
+            int32_t i = cl->idx[k];
+            double dx = cl->x[i] - cl->x[p], dy = cl->y[i] - cl->y[p];
+            double ds = dx * tx + dy * ty;
+            double dn = -(dx * nx + dy * ny);      /* mirrored */
+            double mx = ds * tx + dn * nx, my = ds * ty + dn * ny;
+            double qt0[4], pr0[4], G0[4];
+            shifted_q(prm, n, q, g, qmax, qmin, p, mx, my, qt0);
+            if (!(qt0[3] < 0.0)) return ORA_EPOSITIVITY;
+            ora_q_to_prim(qt0, gamma, pr0);
+            for (int r = 0; r < 4; ++r)
+                if (!isfinite(pr0[r])) return ORA_EPOSITIVITY;
+            ora_split_flux(pr0, nx, ny, -1, gamma, G0);
+            bk[3].ss += ds * ds;
+            bk[3].sn += ds * dn;
+            bk[3].nn += dn * dn;
+            for (int r = 0; r < 4; ++r) {
+                double dG = Ginf[r] - G0[r];
+                bk[3].sG[r] += ds * dG;
+                bk[3].nG[r] += dn * dG;
+            }
+        }
+    }
+    double Rp[4] = {0, 0, 0, 0};
+    for (int b = 0; b < 4; ++b) {
+        if (b == 2 && cl->kind[p] == KIND_WALL) continue;
+        double det = bk[b].ss * bk[b].nn - bk[b].sn * bk[b].sn;
+        for (int r = 0; r < 4; ++r) {
+            double d;
+            if (b < 2) d = (bk[b].sG[r] * bk[b].nn - bk[b].nG[r] * bk[b].sn) / det;
+            else d = (bk[b].nG[r] * bk[b].ss - bk[b].sG[r] * bk[b].sn) / det;
+            Rp[r] += d;
+        }
+    }
+    for (int r = 0; r < 4; ++r) R[r * n + p] = Rp[r];
+    return ORA_OK;
+}
+
 int ora_flux_residual(const ora_cloud *cl, const ora_params *prm, const double *q,
                       const double *g, const double *qmax, const double *qmin, double *R,
                       int64_t *bad_point)
 {
     int64_t n = cl->n;
     double gamma = prm->gamma;
-    int kobc = prm->outer_bc == 1;
     double qinf[4], prinf[4];
     {
         const double pi = 3.14159265358979323846;
@@ -481,98 +621,15 @@ int ora_flux_residual(const ora_cloud *cl, const ora_params *prm, const double *
         ora_prim_to_q(pr, gamma, qinf);
         ora_q_to_prim(qinf, gamma, prinf);
     }
-    *bad_point = -1;
+    int64_t bad = INT64_MAX;
+    int code = ORA_OK;
+#pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < n; ++p) {
-        for (int r = 0; r < 4; ++r) R[r * n + p] = 0.0;
-        if (cl->kind[p] == KIND_OUTER && !kobc) continue;
-        double nx = cl->nx[p], ny = cl->ny[p];
-        double tx = ny, ty = -nx;
-        bucket bk[4];
-        memset(bk, 0, sizeof bk);
-        for (int32_t k = cl->ptr[p]; k < cl->ptr[p + 1]; ++k) {
-            int32_t i = cl->idx[k];
-            uint8_t f = cl->flag[k];
-            if (cl->kind[p] == KIND_WALL) f &= (uint8_t)~SPLIT_N_PLUS;
-            if (cl->kind[p] == KIND_OUTER) f &= (uint8_t)~SPLIT_N_MINUS;
-            if (f == 0) continue;
-            double dx = cl->x[i] - cl->x[p], dy = cl->y[i] - cl->y[p];
-            double ds = dx * tx + dy * ty;
-            double dn = dx * nx + dy * ny;
-            double qti[4], qt0[4];
-            ora_modified_q(cl, prm, q, g, qmax, qmin, p, k, qti, qt0);
-            if (!(qti[3] < 0.0) || !(qt0[3] < 0.0)) { *bad_point = p; return ORA_EPOSITIVITY; }
-            double pri[4], pr0[4];
-            ora_q_to_prim(qti, gamma, pri);
-            ora_q_to_prim(qt0, gamma, pr0);
-            for (int r = 0; r < 4; ++r)
-                if (!isfinite(pri[r]) || !isfinite(pr0[r])) {
-                    *bad_point = p;
-                    return ORA_EPOSITIVITY;
-                }
-            for (int dir = 0; dir < 2; ++dir) {
-                uint8_t fp = dir ? SPLIT_N_PLUS : SPLIT_S_PLUS;
-                uint8_t fm = dir ? SPLIT_N_MINUS : SPLIT_S_MINUS;
-                int sign, b;
-                if (f & fp) { sign = 1; b = 2 * dir; }
-                else if (f & fm) { sign = -1; b = 2 * dir + 1; }
-                else continue;
-                double ex = dir ? nx : tx, ey = dir ? ny : ty;
-                double Gi[4], G0[4];
-                ora_split_flux(pri, ex, ey, sign, gamma, Gi);
-                ora_split_flux(pr0, ex, ey, sign, gamma, G0);
-                bk[b].ss += ds * ds;
-                bk[b].sn += ds * dn;
-                bk[b].nn += dn * dn;
-                for (int r = 0; r < 4; ++r) {
-                    double dG = Gi[r] - G0[r];
-                    bk[b].sG[r] += ds * dG;
-                    bk[b].nG[r] += dn * dG;
-                }
-            }
-        }
-        if (cl->kind[p] == KIND_OUTER) {
-            /* the mirrored n+ stencil at the freestream replaces n- */
-            memset(&bk[3], 0, sizeof bk[3]);
-            double Ginf[4];
-            ora_split_flux(prinf, nx, ny, -1, gamma, Ginf);
-            for (int32_t k = cl->ptr[p]; k < cl->ptr[p + 1]; ++k) {
-                if (!(cl->flag[k] & SPLIT_N_PLUS)) continue;
-                int32_t i = cl->idx[k];
-                double dx = cl->x[i] - cl->x[p], dy = cl->y[i] - cl->y[p];
-                double ds = dx * tx + dy * ty;
-                double dn = -(dx * nx + dy * ny);      /* mirrored */
-                double mx = ds * tx + dn * nx, my = ds * ty + dn * ny;
-                double qt0[4], pr0[4], G0[4];
-                shifted_q(prm, n, q, g, qmax, qmin, p, mx, my, qt0);
-                if (!(qt0[3] < 0.0)) { *bad_point = p; return ORA_EPOSITIVITY; }
-                ora_q_to_prim(qt0, gamma, pr0);
-                for (int r = 0; r < 4; ++r)
-                    if (!isfinite(pr0[r])) { *bad_point = p; return ORA_EPOSITIVITY; }
-                ora_split_flux(pr0, nx, ny, -1, gamma, G0);
-                bk[3].ss += ds * ds;
-                bk[3].sn += ds * dn;
-                bk[3].nn += dn * dn;
-                for (int r = 0; r < 4; ++r) {
-                    double dG = Ginf[r] - G0[r];
-                    bk[3].sG[r] += ds * dG;
-                    bk[3].nG[r] += dn * dG;
-                }
-            }
-        }
-        double Rp[4] = {0, 0, 0, 0};
-        for (int b = 0; b < 4; ++b) {
-            if (b == 2 && cl->kind[p] == KIND_WALL) continue;
-            double det = bk[b].ss * bk[b].nn - bk[b].sn * bk[b].sn;
-            for (int r = 0; r < 4; ++r) {
-                double d;
-                if (b < 2) d = (bk[b].sG[r] * bk[b].nn - bk[b].nG[r] * bk[b].sn) / det;
-                else d = (bk[b].nG[r] * bk[b].ss - bk[b].sG[r] * bk[b].sn) / det;
-                Rp[r] += d;
-            }
-        }
-        for (int r = 0; r < 4; ++r) R[r * n + p] = Rp[r];
+        int st = flux_point(cl, prm, q, g, qmax, qmin, prinf, p, R);
+        if (st) note_failure(p, st, &bad, &code);
     }
-    return ORA_OK;
+    *bad_point = (code != ORA_OK) ? bad : -1;
+    return code;
 }
 
 /* ------------------------------------------------------------------ */
@@ -601,6 +658,7 @@ void ora_state_update(const ora_cloud *cl, const ora_params *prm, int32_t rk, co
                       double *U, const double *R, const double *dt)
 {
     int64_t n = cl->n;
+#pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < n; ++p) {
         if (cl->kind[p] == KIND_OUTER && prm->outer_bc != 1) continue; /* held */
         for (int c = 0; c < 4; ++c) {
