@@ -49,7 +49,7 @@ enum {
     QL_EDEVICE = -4,     /* HIP runtime error; solver poisoned                */
     QL_ENONFINITE = -5,  /* NaN or Inf in a state                             */
     QL_EPOSITIVITY = -6, /* non-positive density/pressure or q4 >= 0          */
-    QL_EDIVERGED = -7,   /* reserved: residual blow-up                        */
+    QL_EDIVERGED = -7,   /* residual blow-up (status of a batched case)       */
     QL_ESTATE = -8       /* call out of order                                 */
 };
 
@@ -170,12 +170,17 @@ int ql_set_state(ql_solver *s, const double *U, int32_t mem, int32_t project_wal
  * over the interior and wall points of each component, and the outer points
  * under the kinetic outer condition; ncase = 1 unless
  * the cloud came from ql_batch_upload).  Enqueues on the solver's
- * stream and synchronises once at the end.
- * Errors: QL_ESTATE, QL_EPOSITIVITY / QL_ENONFINITE (first point of the
- * first failing launch; the state is then undefined), QL_EDEVICE. */
+ * stream; synchronises once at the end when res_hist is not NULL.  With
+ * res_hist NULL it returns once the work is enqueued, and the next call on
+ * the solver collects the outcome: a failure during these iterations is
+ * then returned by that call (ql_residual_norm, ql_fetch_state, ...).
+ * Errors: QL_ESTATE, QL_EPOSITIVITY / QL_ENONFINITE (the smallest failing
+ * point and its own code; the state is then undefined), QL_EDEVICE. */
 int ql_step(ql_solver *s, int32_t n_iter, double *res_hist);
 
-/* Residual norms of the last iteration ql_step ran.  Errors: QL_ESTATE. */
+/* Residual norms of the last iteration ql_step ran (synchronises when that
+ * call returned without a history).  Errors: QL_ESTATE, or the failure of
+ * those iterations. */
 int ql_residual_norm(const ql_solver *s, double out[4]);
 
 /* Copy the conserved state to U[4][n] in caller order (mem 0 host, 1
@@ -218,18 +223,22 @@ int ql_batch_info(const ql_solver *s, int32_t *ncase);
  * drop x its reference norm, or max_iter iterations.  The reference of case
  * c is ref_res[c] when ref_res is not NULL (e.g. the freestream residual
  * that ql_warm_start reports), else the norm of the first iteration of this
- * call.  Every
- * check_every iterations the norms are read back; converged cases retire:
- * their points stop updating and workgroups holding only retired points
- * skip every sweep, while the other cases go on.  graph != 0 captures one
- * iteration into a hipGraph on the solver's stream (re-captured after
- * parameter or buffer changes) and replays it.  iters_out[c] (nullable)
- * receives the iteration at which case c reached the drop (or the
- * iterations run), res_out[c][4] (nullable) its last norms.
- * A case whose state fails (positivity lost, or a non-finite value) is
- * retired with that status while the other cases go on; ql_batch_status
- * reports it.  Its state is left as it was when the failure was found (not
- * usable: set a new state before stepping again).
+ * call.  Retirement happens on the device, after the residual norms of
+ * every iteration: a case whose norm of iteration m (the norm of the state
+ * the iteration started from) reaches the drop keeps the state that
+ * iteration m leaves, which is the state of ql_step(m) from the same start,
+ * and iters_out[c] = m.  Its points stop updating and workgroups holding
+ * only retired points skip every sweep, while the other cases go on.  The
+ * host reads the active flags every check_every iterations only to stop
+ * once none is left.  graph != 0 captures one iteration into a hipGraph on
+ * the solver's stream (re-captured after parameter or buffer changes) and
+ * replays it.  iters_out[c] (nullable) receives the iterations case c ran,
+ * res_out[c][4] (nullable) the norms of its last one.
+ * A case whose state fails (positivity lost, or a non-finite value) in
+ * iteration m is retired at the end of m with that status, as is a case
+ * whose norm exceeds 1e8 x its reference (QL_EDIVERGED); the other cases go
+ * on, and ql_batch_status reports every retired case's status.  A failed
+ * case's state is not usable: set a new state before stepping again.
  * Errors: as ql_step for failures that name no case; QL_EINVAL (drop <= 0,
  * max_iter < 0, check_every < 1, a reference <= 0 or not finite). */
 int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_every, int32_t graph,
@@ -237,7 +246,7 @@ int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_ever
 
 /* Per-case outcome of the last ql_batch_run: status[c] = QL_OK (reached the
  * drop or ran max_iter), QL_EPOSITIVITY or QL_ENONFINITE (case c failed and
- * was retired).  status holds ncase entries (ql_batch_info); all QL_OK
+ * was retired), QL_EDIVERGED (its norm blew up).  status holds ncase entries (ql_batch_info); all QL_OK
  * before any run.  Errors: QL_EINVAL (NULL), QL_ESTATE (no cloud). */
 int ql_batch_status(const ql_solver *s, int32_t *status);
 

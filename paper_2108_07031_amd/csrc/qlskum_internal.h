@@ -18,6 +18,17 @@ enum Kind : uint8_t { kInterior = 0, kWall = 1, kOuter = 2 };
 enum Split : uint8_t { kSPlus = 1, kSMinus = 2, kNPlus = 4, kNMinus = 8 };
 enum ErrCode : int { kErrNone = 0, kErrSingular = 1, kErrPositivity = 2, kErrNonFinite = 3 };
 
+// Device error word: (p << 8) | code of the smallest failing point p, set by
+// atomicMin; kErrClear when no point failed.
+using ErrWord = unsigned long long;
+constexpr ErrWord kErrClear = ~0ull;
+inline int err_point(ErrWord w) { return w == kErrClear ? -1 : (int)(w >> 8); }
+inline int err_code(ErrWord w) { return w == kErrClear ? kErrNone : (int)(w & 0xff); }
+
+// a batched case whose residual norm exceeds this multiple of its reference
+// norm has diverged
+constexpr double kDiverged = 1e8;
+
 // Point cloud on the device, in the library's (reordered) point order.
 struct DevCloud {
     int n;
@@ -46,6 +57,8 @@ struct DevCloud {
     const int *case_of;
     const uint8_t *case_active;
     const uint8_t *tile_active;
+    // batched runs: error word of each case [ncase] (nullable)
+    ErrWord *case_err;
     // conserved freestream of each case [ncase][4] (the kinetic outer
     // condition's far-field Maxwellian)
     const double *uinf;
@@ -71,8 +84,22 @@ struct Shadow {
     float4 *qmm32;
 };
 
-// Error word on the device: err[0] = smallest failing point (INT_MAX when
-// none), err[1] = ErrCode of some failing point.
+// Retirement of batched cases, applied on the device after every
+// iteration's residual norms (on = 0: plain iterations).  A case stops
+// (active[c] = 0) at the iteration whose norm is <= *drop * ref[c] (ref[c] < 0
+// takes the case's first norm), whose norm exceeds kDiverged * ref[c] or is
+// not a number, or in which one of its points failed (case_err[c] set);
+// iters[c] counts the iterations it ran, last[c][4] holds their last norms.
+struct Retire {
+    int on;
+    const double *drop;
+    double *ref;
+    int *iters;
+    double *last;
+    uint8_t *active;
+    const ErrWord *case_err;
+};
+
 int num_blocks(int n);
 int num_flux_tiles(int n);
 
@@ -80,8 +107,8 @@ int num_flux_tiles(int n);
 // the kinetic outer condition), err every other singular matrix.
 hipError_t launch_setup(hipStream_t st, int n, const double2 *xy, const double2 *nrm,
                         const uint8_t *kind, const int *ptr, const int *idx, uint8_t *flag,
-                        int classify, double *lsw, double *lsi, double *dmin, int *err,
-                        int *err_outer);
+                        int classify, double *lsw, double *lsi, double *dmin, ErrWord *err,
+                        ErrWord *err_outer);
 hipError_t launch_freestream(hipStream_t st, int n, const double2 *nrm, const uint8_t *kind,
                              const int *case_of, const double *uinf, double *U);
 hipError_t launch_permute_state(hipStream_t st, int n, const double *Uuser, const int *perm,
@@ -89,7 +116,7 @@ hipError_t launch_permute_state(hipStream_t st, int n, const double *Uuser, cons
 hipError_t launch_unpermute_state(hipStream_t st, int n, const double *U, const int *perm,
                                   double *Uuser);
 hipError_t launch_prep(hipStream_t st, const DevCloud &c, const FlowParams &fp, const double *U,
-                       double *Un, double2 *q, double *dt, float4 *q32, int *err);
+                       double *Un, double2 *q, double *dt, float4 *q32, ErrWord *err);
 // q-derivatives (tiled like the flux sweep; lds_budget as there): first
 // pass with the limiter bounds (qmm: qmax - q and qmin - q per point), and
 // one inner iteration from the first pass g0 and the previous iterate gprev.
@@ -109,14 +136,14 @@ hipError_t launch_gradk(hipStream_t st, const DevCloud &c, int lds_budget, const
 hipError_t launch_flux(hipStream_t st, const DevCloud &c, const FlowParams &fp, int stage,
                        int lds_budget, const double2 *q, const double2 *g, const double2 *qmm,
                        double *U, double *Un, double *dt, double2 *qnext, double *Rout,
-                       float4 *q32next, int *err, int split, double *const Rpart[2]);
+                       float4 *q32next, ErrWord *err, int split, double *const Rpart[2]);
 // mixed precision: reconstruction, limiter and split fluxes in FP32 from the
 // shadows q32, g32, qmm32; weights, residual sums and the update in FP64.
 hipError_t launch_flux_mixed(hipStream_t st, const DevCloud &c, const FlowParams &fp, int stage,
                              int lds_budget, const double2 *q, const float4 *q32,
                              const float4 *g32, const float4 *qmm32, double *U, double *Un,
                              double *dt, double2 *qnext, float4 *q32next, double *Rout,
-                             int *err);
+                             ErrWord *err);
 // warm start: de-standardisation of the network's (rho, u1, u2, p) and the
 // lower bound of rho and p relative to the freestream
 struct WarmScale {
@@ -130,10 +157,12 @@ hipError_t launch_select_state(hipStream_t st, int n, const int *case_of, const 
                                const double *Uw, double *U);
 hipError_t launch_wall_distance(hipStream_t st, int n, const double2 *xy, const int *case_of,
                                 const int *wall_lo, const int *wall, double *d);
-// residual norms per case into history row *ctr (then *ctr += 1)
+// residual norms per case into history row *ctr (then *ctr += 1); with
+// rt.on, the retirement of cases and the tile activity that follows from it
 hipError_t launch_resnorm(hipStream_t st, const double *R, int n, int nchunk, const int *chunk_beg,
                           double *part, int ncase, const int *chunk_ptr, const double *inv_nupd,
-                          int *ctr, int cap, double *hist);
+                          int *ctr, int cap, double *hist, const Retire &rt,
+                          const int *case_of, uint8_t *tile_active);
 hipError_t launch_forces(hipStream_t st, int nw, const int *wall, const double2 *xy,
                          const double2 *nrm, const double *U, int n, double gamma, double pinf,
                          double *scratch, double *out);

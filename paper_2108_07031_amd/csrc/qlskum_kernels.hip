@@ -41,9 +41,16 @@ __device__ __forceinline__ int logical_block() {
 
 __device__ __forceinline__ int point_id() { return logical_block() * kBlock + threadIdx.x; }
 
-__device__ __forceinline__ void report(int *err, int p, int code) {
-    atomicMin(&err[0], p);
-    atomicExch(&err[1], code);
+// The point and its code travel in one word, (p << 8) | code, so the
+// smallest failing point and the code it reported are always read together.
+__device__ __forceinline__ void report(ErrWord *err, int p, int code) {
+    atomicMin(err, ((ErrWord)(unsigned)p << 8) | (ErrWord)(unsigned)code);
+}
+
+// report to the solver's word and, in a batch, to the point's case word
+__device__ __forceinline__ void report_pt(const DevCloud &cl, ErrWord *err, int p, int code) {
+    report(err, p, code);
+    if (cl.case_err) report(cl.case_err + cl.case_of[p], p, code);
 }
 
 __device__ __forceinline__ void load4(const double2 *a, int p, double v[4]) {
@@ -62,12 +69,26 @@ __device__ __forceinline__ void store4(double2 *a, int p, const double v[4]) {
     a[2 * p + 1] = make_double2(v[2], v[3]);
 }
 
+// Value of lane l ^ 1 (CTRL kQuadXor1) or l ^ 2 (kQuadXor2) of the same group
+// of four lanes: a DPP quad permutation of each 32-bit half (a VALU move, no
+// LDS round trip).  Every lane of the quad must be active.
+static_assert(kFluxLanes == 4, "the lane groups of the tiled sweeps are DPP quads");
+constexpr int kQuadXor1 = 0xB1;  // quad_perm [1, 0, 3, 2]
+constexpr int kQuadXor2 = 0x4E;  // quad_perm [2, 3, 0, 1]
+template <int CTRL>
+__device__ __forceinline__ double quad_swap(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
 // Sum over the kFluxLanes lanes that serve one point, in the fixed order
 // (l0 + l1) + (l2 + l3); every lane of the group receives the same value
 // (floating-point addition is commutative).
 __device__ __forceinline__ double lane_group_sum(double v) {
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
+    v += quad_swap<kQuadXor1>(v);
+    v += quad_swap<kQuadXor2>(v);
     return v;
 }
 
@@ -123,8 +144,8 @@ __global__ void __launch_bounds__(kBlock) k_setup(int n, const double2 *__restri
                                                   const int *__restrict__ idx, uint8_t *flag,
                                                   int classify, double *__restrict__ lsw,
                                                   double *__restrict__ lsi,
-                                                  double *__restrict__ dmin, int *err,
-                                                  int *err_outer) {
+                                                  double *__restrict__ dmin, ErrWord *err,
+                                                  ErrWord *err_outer) {
 #pragma clang fp contract(off)
     const int p = point_id();
     if (p >= n) return;
@@ -203,8 +224,8 @@ __global__ void __launch_bounds__(kBlock) k_setup(int n, const double2 *__restri
 
 hipError_t launch_setup(hipStream_t st, int n, const double2 *xy, const double2 *nrm,
                         const uint8_t *kind, const int *ptr, const int *idx, uint8_t *flag,
-                        int classify, double *lsw, double *lsi, double *dmin, int *err,
-                        int *err_outer) {
+                        int classify, double *lsw, double *lsi, double *dmin, ErrWord *err,
+                        ErrWord *err_outer) {
     hipLaunchKernelGGL(k_setup, dim3(num_blocks(n)), dim3(kBlock), 0, st, n, xy, nrm, kind, ptr,
                        idx, flag, classify, lsw, lsi, dmin, err, err_outer);
     return hipGetLastError();
@@ -381,16 +402,17 @@ __global__ void __launch_bounds__(kBlock) k_prep(DevCloud cl, FlowParams fp,
                                                  const double *__restrict__ U,
                                                  double *__restrict__ Un, double2 *__restrict__ q,
                                                  double *__restrict__ dt, float4 *__restrict__ q32,
-                                                 int *err) {
+                                                 ErrWord *err) {
     const int n = cl.n;
     const int p = point_id();
     if (p >= n) return;
+    if (cl.case_active && !cl.case_active[cl.case_of[p]]) return;  // retired case: frozen
     double v[4], qq[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) v[c] = U[(size_t)c * n + p];
     const int e = cons_to_q(v, fp, qq);
     if (e != kErrNone) {
-        report(err, p, e);
+        report_pt(cl, err, p, e);
         qq[0] = qq[1] = qq[2] = 0.0;
         qq[3] = -1.0;
     }
@@ -402,7 +424,7 @@ __global__ void __launch_bounds__(kBlock) k_prep(DevCloud cl, FlowParams fp,
 }
 
 hipError_t launch_prep(hipStream_t st, const DevCloud &c, const FlowParams &fp, const double *U,
-                       double *Un, double2 *q, double *dt, float4 *q32, int *err) {
+                       double *Un, double2 *q, double *dt, float4 *q32, ErrWord *err) {
     hipLaunchKernelGGL(k_prep, dim3(num_blocks(c.n)), dim3(kBlock), 0, st, c, fp, U, Un, q, dt,
                        q32, err);
     return hipGetLastError();
@@ -420,13 +442,13 @@ hipError_t launch_prep(hipStream_t st, const DevCloud &c, const FlowParams &fp, 
 namespace {
 
 __device__ __forceinline__ double lane_group_max(double v) {
-    v = fmax(v, __shfl_xor(v, 1, 64));
-    return fmax(v, __shfl_xor(v, 2, 64));
+    v = fmax(v, quad_swap<kQuadXor1>(v));
+    return fmax(v, quad_swap<kQuadXor2>(v));
 }
 
 __device__ __forceinline__ double lane_group_min(double v) {
-    v = fmin(v, __shfl_xor(v, 1, 64));
-    return fmin(v, __shfl_xor(v, 2, 64));
+    v = fmin(v, quad_swap<kQuadXor1>(v));
+    return fmin(v, quad_swap<kQuadXor2>(v));
 }
 
 // tile set-up shared by the tiled sweeps: image size ns and whether it is
@@ -457,6 +479,43 @@ __device__ __forceinline__ int slot_point(const DevCloud &cl, const TileInfo &ti
 }
 
 }  // namespace
+
+// Entry loops of the q-derivative sweeps, one instantiation per place the
+// gathered records live (LDS image or memory): a loop whose loads may come
+// from either would be compiled to generic (flat) loads, which go through
+// the vector-memory path even for LDS and wait on both counters.
+
+// first pass: sums of dx dq, dy dq and the componentwise max / min over the
+// entries k0 + sub, k0 + sub + kFluxLanes, ... < k1 of point p
+template <bool LDS>
+__device__ __forceinline__ void grad0_entries(const DevCloud &cl, const double2 *lds,
+                                              const double2 *q, int k0, int k1, int sub,
+                                              const double qp[4], double2 P, double sx[4],
+                                              double sy[4], double mx[4], double mn[4]) {
+    constexpr int kRec = 3;
+    for (int k = k0 + sub; k < k1; k += kFluxLanes) {
+        double qi[4];
+        double2 Q;
+        if constexpr (LDS) {
+            const double2 *r = lds + kRec * (int)cl.flidx[k];
+            qi[0] = r[0].x; qi[1] = r[0].y; qi[2] = r[1].x; qi[3] = r[1].y;
+            Q = r[2];
+        } else {
+            const int i = cl.idx[k];
+            load4(q, i, qi);
+            Q = cl.xy[i];
+        }
+        const double dx = Q.x - P.x, dy = Q.y - P.y;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double dq = qi[r] - qp[r];
+            sx[r] = fma(dx, dq, sx[r]);
+            sy[r] = fma(dy, dq, sy[r]);
+            mx[r] = fmax(mx[r], qi[r]);
+            mn[r] = fmin(mn[r], qi[r]);
+        }
+    }
+}
 
 // first pass: full-stencil least squares of dq_i = q_i - q_p (eq. (11)), and
 // the componentwise max / min of q over the point and its stencil (bounds of
@@ -493,40 +552,22 @@ __global__ void __launch_bounds__(kBlock) k_grad0(DevCloud cl, int cap,
     double mx[4] = {0, 0, 0, 0}, mn[4] = {0, 0, 0, 0};
     if (j < ti.nown) {
         double qp[4];
-        double2 P;
+        // the own position from memory on both paths (one load per point; a
+        // value that may come from LDS or memory would be a generic load)
+        const double2 P = cl.xy[p];
         if (ti.in_lds) {
             const double2 *r = lds + kRec * j;
             qp[0] = r[0].x; qp[1] = r[0].y; qp[2] = r[1].x; qp[3] = r[1].y;
-            P = r[2];
         } else {
             load4(q, p, qp);
-            P = cl.xy[p];
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) mx[r] = mn[r] = qp[r];
-        const int k1 = cl.ptr[p + 1];
-        for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
-            double qi[4];
-            double2 Q;
-            if (ti.in_lds) {
-                const double2 *r = lds + kRec * (int)cl.flidx[k];
-                qi[0] = r[0].x; qi[1] = r[0].y; qi[2] = r[1].x; qi[3] = r[1].y;
-                Q = r[2];
-            } else {
-                const int i = cl.idx[k];
-                load4(q, i, qi);
-                Q = cl.xy[i];
-            }
-            const double dx = Q.x - P.x, dy = Q.y - P.y;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const double dq = qi[r] - qp[r];
-                sx[r] = fma(dx, dq, sx[r]);
-                sy[r] = fma(dy, dq, sy[r]);
-                mx[r] = fmax(mx[r], qi[r]);
-                mn[r] = fmin(mn[r], qi[r]);
-            }
-        }
+        const int k0 = cl.ptr[p], k1 = cl.ptr[p + 1];
+        if (ti.in_lds)
+            grad0_entries<true>(cl, lds, q, k0, k1, sub, qp, P, sx, sy, mx, mn);
+        else
+            grad0_entries<false>(cl, lds, q, k0, k1, sub, qp, P, sx, sy, mx, mn);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -570,6 +611,44 @@ __global__ void __launch_bounds__(kBlock) k_grad0(DevCloud cl, int cap,
 // entry slots an inner-iteration workgroup stages in LDS (tiles with more
 // entries read them from memory)
 constexpr int kCapE = 2048;
+constexpr int kLdsBytes = 160 * 1024;  // LDS one workgroup may allocate on gfx950
+
+// inner iteration: sums of dx f, dy f with f = dx g_x,i + dy g_y,i over the
+// entries of point p.  SRC 0: records and entry slots in LDS; 1: records in
+// LDS, entry slots from memory; 2: records from memory.
+template <int SRC>
+__device__ __forceinline__ void gradk_entries(const DevCloud &cl, const double2 *lds,
+                                              const uint16_t *eidx, int e0,
+                                              const double2 *gprev, int kb, int k1, int sub,
+                                              double2 P, double sx[4], double sy[4]) {
+    constexpr int kRec = 5;
+#pragma unroll 1
+    for (int k = kb + sub; k < k1; k += kFluxLanes) {
+        double gi[8];
+        double2 Q;
+        if constexpr (SRC < 2) {
+            const int li = (SRC == 0) ? (int)eidx[k - e0] : (int)cl.flidx[k];
+            const double2 *r = lds + kRec * li;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                gi[2 * m] = r[m].x;
+                gi[2 * m + 1] = r[m].y;
+            }
+            Q = r[4];
+        } else {
+            const int i = cl.idx[k];
+            load8(gprev, i, gi);
+            Q = cl.xy[i];
+        }
+        const double dx = Q.x - P.x, dy = Q.y - P.y;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double f = fma(dx, gi[r], dy * gi[4 + r]);
+            sx[r] = fma(dx, f, sx[r]);
+            sy[r] = fma(dy, f, sy[r]);
+        }
+    }
+}
 
 // one inner iteration (eq. (29)).  The least squares is linear in its data:
 //   g^k = LS(dq_i) - 1/2 LS(d.(g^{k-1}_i - g^{k-1}_p)) = g0 - 1/2 LS(...)
@@ -628,46 +707,13 @@ __global__ void __launch_bounds__(kBlock) k_gradk(DevCloud cl, int cap,
     __syncthreads();
     double sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
     if (own) {
-        double gp[8];
-        double2 P;
-        if (ti.in_lds) {
-            const double2 *r = lds + kRec * j;
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                gp[2 * m] = r[m].x;
-                gp[2 * m + 1] = r[m].y;
-            }
-            P = r[4];
-        } else {
-            load8(gprev, p, gp);
-            P = cl.xy[p];
-        }
-#pragma unroll 1
-        for (int k = kb + sub; k < k1; k += kFluxLanes) {
-            double gi[8];
-            double2 Q;
-            if (ti.in_lds) {
-                const int li = e_lds ? (int)eidx[k - e0] : (int)cl.flidx[k];
-                const double2 *r = lds + kRec * li;
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    gi[2 * m] = r[m].x;
-                    gi[2 * m + 1] = r[m].y;
-                }
-                Q = r[4];
-            } else {
-                const int i = cl.idx[k];
-                load8(gprev, i, gi);
-                Q = cl.xy[i];
-            }
-            const double dx = Q.x - P.x, dy = Q.y - P.y;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const double f = fma(dx, gi[r], dy * gi[4 + r]);
-                sx[r] = fma(dx, f, sx[r]);
-                sy[r] = fma(dy, f, sy[r]);
-            }
-        }
+        const double2 P = cl.xy[p];  // from memory on both paths (see k_grad0)
+        if (e_lds)
+            gradk_entries<0>(cl, lds, eidx, e0, gprev, kb, k1, sub, P, sx, sy);
+        else if (ti.in_lds)
+            gradk_entries<1>(cl, lds, eidx, e0, gprev, kb, k1, sub, P, sx, sy);
+        else
+            gradk_entries<2>(cl, lds, eidx, e0, gprev, kb, k1, sub, P, sx, sy);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -687,7 +733,7 @@ __global__ void __launch_bounds__(kBlock) k_gradk(DevCloud cl, int cap,
     if (g32) {
         // the FP32 shadow packs (q_x[0..3]) and (q_y[0..3]): lanes 0,1 and 2,3
         // hold halves of one float4, combined through a shuffle of partner lanes
-        const double o0 = __shfl_xor(v[0], 1, 64), o1 = __shfl_xor(v[1], 1, 64);
+        const double o0 = quad_swap<kQuadXor1>(v[0]), o1 = quad_swap<kQuadXor1>(v[1]);
         if ((sub & 1) == 0)
             g32[2 * p + (sub >> 1)] =
                 make_float4((float)v[0], (float)v[1], (float)o0, (float)o1);
@@ -717,7 +763,8 @@ hipError_t launch_grad0(hipStream_t st, const DevCloud &c, int lds_budget, const
 hipError_t launch_gradk(hipStream_t st, const DevCloud &c, int lds_budget, const double2 *g0,
                         const double2 *gprev, double2 *gnext, float4 *g32) {
     const int rec = 5 * (int)sizeof(double2);
-    const int cap = lds_cap(c, lds_budget, rec);
+    // the image and the entry slots share the workgroup's 160 KB of LDS
+    const int cap = min(lds_cap(c, lds_budget, rec), (kLdsBytes - 2 * kCapE) / rec);
     const size_t shmem = cap > 0 ? (size_t)cap * rec + 2 * kCapE : 0;
     hipLaunchKernelGGL(k_gradk, dim3(num_flux_tiles(c.n)), dim3(kBlock), shmem, st, c,
                        cap, g0, gprev, gnext, g32);
@@ -1009,7 +1056,7 @@ __device__ __forceinline__ bool freestream_flux(const double *u, double2 N, cons
 __device__ __forceinline__ void rk_update(const DevCloud &cl, const FlowParams &fp, int stage,
                                           int p, uint8_t kd, double2 N, const double R[4],
                                           double *U, double *Un, double *dt, double2 *qnext,
-                                          float4 *q32next, int *err) {
+                                          float4 *q32next, ErrWord *err) {
     const int n = cl.n;
     const double h = 0.5 * dt[p];
     double v[4];
@@ -1027,7 +1074,7 @@ __device__ __forceinline__ void rk_update(const DevCloud &cl, const FlowParams &
     double qq[4];
     const int e = cons_to_q(v, fp, qq);
     if (e != kErrNone) {
-        report(err, p, e);
+        report_pt(cl, err, p, e);
         qq[0] = qq[1] = qq[2] = 0.0;
         qq[3] = -1.0;
     }
@@ -1066,6 +1113,94 @@ __device__ __forceinline__ void rk_update(const DevCloud &cl, const FlowParams &
 // ---------------------------------------------------------------------------
 int num_flux_tiles(int n) { return (n + kFluxTile - 1) / kFluxTile; }
 
+namespace {
+
+// Residual sums of live point p (slot j of its tile) over its entries
+// sub, sub + kFluxLanes, ...; IN_LDS: the records come from the tile's LDS
+// image, else from memory (one instantiation each, so that no load is
+// generic).  Reports a failed reconstruction.
+template <bool IN_LDS, bool LIMITER, int POW, bool FIRST, int M, bool KOBC>
+__device__ __forceinline__ void flux_point(const DevCloud &cl, const FlowParams &fp,
+                                           const double2 *lds, int j, int p, int sub, uint8_t kd,
+                                           double2 N, const double2 *q, const double2 *g,
+                                           const double2 *qmm, double R[4], ErrWord *err) {
+    constexpr int kRec = FIRST ? 3 : (LIMITER ? 11 : 7);
+    double qp[4], gp[8], bp[8], w[8];
+    const double2 P = cl.xy[p];
+    if constexpr (IN_LDS) {
+        const double2 *r = lds + kRec * j;
+        qp[0] = r[0].x; qp[1] = r[0].y; qp[2] = r[1].x; qp[3] = r[1].y;
+#pragma unroll
+        for (int m = 0; m < 4 && !FIRST; ++m) {
+            gp[2 * m] = r[2 + m].x;
+            gp[2 * m + 1] = r[2 + m].y;
+            if (LIMITER) {
+                bp[2 * m] = r[6 + m].x;
+                bp[2 * m + 1] = r[6 + m].y;
+            }
+        }
+    } else {
+        load4(q, p, qp);
+        if (!FIRST) load8(g, p, gp);
+        if (LIMITER) load8(qmm, p, bp);
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) w[m] = cl.lsw[8 * p + m];
+    // walls drop n+ (its stencil lies in the body), outer points n- (it
+    // lies beyond the far field; the mirrored term below replaces it)
+    uint8_t fmask = ((kd == kWall) ? uint8_t(~kNPlus) : uint8_t(0xff)) & uint8_t(M);
+    if constexpr (KOBC) {
+        if (kd == kOuter) fmask &= uint8_t(~kNMinus);
+    }
+    const int k1 = cl.ptr[p + 1];
+    bool ok = true;
+#pragma unroll 2
+    for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
+        const uint8_t f = cl.flag[k] & fmask;
+        if (f == 0) continue;
+        double qi[4], gi[8], bi[8];
+        double2 Q;
+        if constexpr (IN_LDS) {
+            const double2 *r = lds + kRec * (int)cl.flidx[k];
+            qi[0] = r[0].x; qi[1] = r[0].y; qi[2] = r[1].x; qi[3] = r[1].y;
+#pragma unroll
+            for (int m = 0; m < 4 && !FIRST; ++m) {
+                gi[2 * m] = r[2 + m].x;
+                gi[2 * m + 1] = r[2 + m].y;
+                if (LIMITER) {
+                    bi[2 * m] = r[6 + m].x;
+                    bi[2 * m + 1] = r[6 + m].y;
+                }
+            }
+            Q = r[kRec - 1];
+        } else {
+            const int i = cl.idx[k];
+            load4(q, i, qi);
+            if (!FIRST) load8(g, i, gi);
+            if (LIMITER) load8(qmm, i, bi);
+            Q = cl.xy[i];
+        }
+        ok &= flux_entry<LIMITER, POW, FIRST, M>(f, Q.x - P.x, Q.y - P.y, N, qi, gi, bi, qp, gp,
+                                                 bp, w, fp, R);
+    }
+    if constexpr (KOBC && (M & kNMinus)) {
+        if (kd == kOuter) {
+            double Ginf[4];
+            ok &= freestream_flux<POW>(cl.uinf + 4 * cl.case_of[p], N, fp, Ginf);
+            for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
+                if (!(cl.flag[k] & kNPlus)) continue;
+                const double2 Q = IN_LDS ? lds[kRec * (int)cl.flidx[k] + kRec - 1]
+                                         : cl.xy[cl.idx[k]];
+                ok &= mirror_entry<LIMITER, POW, FIRST>(Q.x - P.x, Q.y - P.y, N, qp, gp, bp, w,
+                                                        Ginf, fp, R);
+            }
+        }
+    }
+    if (!ok) report_pt(cl, err, p, kErrPositivity);
+}
+
+}  // namespace
+
 template <bool LIMITER, int POW, bool FIRST, int M, bool KOBC>
 // Held to 3 waves per SIMD (at most 168 VGPRs), which the straight-line
 // two-direction body of flux_entry would otherwise exceed.
@@ -1079,7 +1214,7 @@ k_flux(DevCloud cl, FlowParams fp, int stage, int cap,
                                                  double *__restrict__ dt,
                                                  double2 *__restrict__ qnext,
                                                  double *__restrict__ Rout,
-                                                 float4 *__restrict__ q32next, int *err) {
+                                                 float4 *__restrict__ q32next, ErrWord *err) {
     // slot record (double2): q 0..1, g 2..5, bound offsets 6..9, position last
     // (first order: q and position only)
     constexpr int kRec = FIRST ? 3 : (LIMITER ? 11 : 7);
@@ -1135,80 +1270,12 @@ k_flux(DevCloud cl, FlowParams fp, int stage, int cap,
     double2 N = make_double2(0.0, 0.0);
     if (live) {
         N = cl.nrm[p];
-        double qp[4], gp[8], bp[8], w[8];
-        double2 P;
-        if (in_lds) {
-            const double2 *r = lds + kRec * j;
-            qp[0] = r[0].x; qp[1] = r[0].y; qp[2] = r[1].x; qp[3] = r[1].y;
-#pragma unroll
-            for (int m = 0; m < 4 && !FIRST; ++m) {
-                gp[2 * m] = r[2 + m].x;
-                gp[2 * m + 1] = r[2 + m].y;
-                if (LIMITER) {
-                    bp[2 * m] = r[6 + m].x;
-                    bp[2 * m + 1] = r[6 + m].y;
-                }
-            }
-            P = r[kRec - 1];
-        } else {
-            load4(q, p, qp);
-            if (!FIRST) load8(g, p, gp);
-            if (LIMITER) load8(qmm, p, bp);
-            P = cl.xy[p];
-        }
-#pragma unroll
-        for (int m = 0; m < 8; ++m) w[m] = cl.lsw[8 * p + m];
-        // walls drop n+ (its stencil lies in the body), outer points n- (it
-        // lies beyond the far field; the mirrored term below replaces it)
-        uint8_t fmask = ((kd == kWall) ? uint8_t(~kNPlus) : uint8_t(0xff)) & uint8_t(M);
-        if constexpr (KOBC) {
-            if (kd == kOuter) fmask &= uint8_t(~kNMinus);
-        }
-        const int k1 = cl.ptr[p + 1];
-        bool ok = true;
-#pragma unroll 2
-        for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
-            const uint8_t f = cl.flag[k] & fmask;
-            if (f == 0) continue;
-            double qi[4], gi[8], bi[8];
-            double2 Q;
-            if (in_lds) {
-                const double2 *r = lds + kRec * (int)cl.flidx[k];
-                qi[0] = r[0].x; qi[1] = r[0].y; qi[2] = r[1].x; qi[3] = r[1].y;
-#pragma unroll
-                for (int m = 0; m < 4 && !FIRST; ++m) {
-                    gi[2 * m] = r[2 + m].x;
-                    gi[2 * m + 1] = r[2 + m].y;
-                    if (LIMITER) {
-                        bi[2 * m] = r[6 + m].x;
-                        bi[2 * m + 1] = r[6 + m].y;
-                    }
-                }
-                Q = r[kRec - 1];
-            } else {
-                const int i = cl.idx[k];
-                load4(q, i, qi);
-                if (!FIRST) load8(g, i, gi);
-                if (LIMITER) load8(qmm, i, bi);
-                Q = cl.xy[i];
-            }
-            ok &= flux_entry<LIMITER, POW, FIRST, M>(f, Q.x - P.x, Q.y - P.y, N, qi, gi, bi, qp,
-                                                     gp, bp, w, fp, R);
-        }
-        if constexpr (KOBC && (M & kNMinus)) {
-            if (kd == kOuter) {
-                double Ginf[4];
-                ok &= freestream_flux<POW>(cl.uinf + 4 * cl.case_of[p], N, fp, Ginf);
-                for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
-                    if (!(cl.flag[k] & kNPlus)) continue;
-                    const double2 Q = in_lds ? lds[kRec * (int)cl.flidx[k] + kRec - 1]
-                                             : cl.xy[cl.idx[k]];
-                    ok &= mirror_entry<LIMITER, POW, FIRST>(Q.x - P.x, Q.y - P.y, N, qp, gp, bp,
-                                                            w, Ginf, fp, R);
-                }
-            }
-        }
-        if (!ok) report(err, p, kErrPositivity);
+        if (in_lds)
+            flux_point<true, LIMITER, POW, FIRST, M, KOBC>(cl, fp, lds, j, p, sub, kd, N, q, g,
+                                                           qmm, R, err);
+        else
+            flux_point<false, LIMITER, POW, FIRST, M, KOBC>(cl, fp, lds, j, p, sub, kd, N, q, g,
+                                                            qmm, R, err);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) R[r] = lane_group_sum(R[r]);
@@ -1265,7 +1332,7 @@ void dispatch_flow(const FlowParams &fp, F &&f) {
 hipError_t launch_flux(hipStream_t st, const DevCloud &c, const FlowParams &fp, int stage,
                        int lds_budget, const double2 *q, const double2 *g, const double2 *qmm,
                        double *U, double *Un, double *dt, double2 *qnext, double *Rout,
-                       float4 *q32next, int *err, int split, double *const Rpart[2]) {
+                       float4 *q32next, ErrWord *err, int split, double *const Rpart[2]) {
     const bool first = fp.order == 1;
     const int rec = (first ? 3 : fp.limiter ? 11 : 7) * (int)sizeof(double2);
     const int cap = lds_cap(c, lds_budget, rec);
@@ -1485,6 +1552,100 @@ __device__ __forceinline__ bool freestream_flux_f(const double *u, double2 N,
     return ok;
 }
 
+// Mixed-precision residual sums of live point p, as flux_point: IN_LDS
+// selects where the FP32 records and positions come from.
+template <bool IN_LDS, bool LIMITER, int POW, bool FIRST, bool KOBC>
+__device__ __forceinline__ void flux_point_f(const DevCloud &cl, const FlowParams &fp,
+                                             const float4 *ldsf, const double2 *lxy, int j, int p,
+                                             int sub, uint8_t kd, double2 N,
+                                             const float4 *q32, const float4 *g32,
+                                             const float4 *qmm32, double R[4], ErrWord *err) {
+    constexpr int kRec = FIRST ? 1 : (LIMITER ? 5 : 3);
+    const float gm1inv = (float)fp.gm1inv;
+    const float vk = (float)fp.venkat_k;
+    float qp[4], gp[8], bp[8];
+    double w[8];
+    const double2 P = cl.xy[p];
+    if constexpr (IN_LDS) {
+        const float4 *r = ldsf + kRec * j;
+        unpack(r[0], qp);
+        if (!FIRST) {
+            unpack(r[1], gp);
+            unpack(r[2], gp + 4);
+        }
+        if (LIMITER) {
+            unpack(r[3], bp);
+            unpack(r[4], bp + 4);
+        }
+    } else {
+        unpack(q32[p], qp);
+        if (!FIRST) {
+            unpack(g32[2 * p], gp);
+            unpack(g32[2 * p + 1], gp + 4);
+        }
+        if (LIMITER) {
+            unpack(qmm32[2 * p], bp);
+            unpack(qmm32[2 * p + 1], bp + 4);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) w[m] = cl.lsw[8 * p + m];
+    uint8_t fmask = (kd == kWall) ? uint8_t(~kNPlus) : uint8_t(0xff);
+    if constexpr (KOBC) {
+        if (kd == kOuter) fmask &= uint8_t(~kNMinus);
+    }
+    const int k1 = cl.ptr[p + 1];
+    bool ok = true;
+#pragma unroll 2
+    for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
+        const uint8_t f = cl.flag[k] & fmask;
+        if (f == 0) continue;
+        float qi[4], gi[8], bi[8];
+        double2 Q;
+        if constexpr (IN_LDS) {
+            const int s = cl.flidx[k];
+            const float4 *r = ldsf + kRec * s;
+            unpack(r[0], qi);
+            if (!FIRST) {
+                unpack(r[1], gi);
+                unpack(r[2], gi + 4);
+            }
+            if (LIMITER) {
+                unpack(r[3], bi);
+                unpack(r[4], bi + 4);
+            }
+            Q = lxy[s];
+        } else {
+            const int i = cl.idx[k];
+            unpack(q32[i], qi);
+            if (!FIRST) {
+                unpack(g32[2 * i], gi);
+                unpack(g32[2 * i + 1], gi + 4);
+            }
+            if (LIMITER) {
+                unpack(qmm32[2 * i], bi);
+                unpack(qmm32[2 * i + 1], bi + 4);
+            }
+            Q = cl.xy[i];
+        }
+        ok &= flux_entry_f<LIMITER, POW, FIRST>(f, Q.x - P.x, Q.y - P.y, N, qi, gi, bi, qp, gp,
+                                                bp, w, gm1inv, vk, R);
+    }
+    if constexpr (KOBC) {
+        if (kd == kOuter) {
+            float Ginf[4];
+            ok &= freestream_flux_f<POW>(cl.uinf + 4 * cl.case_of[p], N, fp, Ginf);
+            for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
+                if (!(cl.flag[k] & kNPlus)) continue;
+                const double2 Q = IN_LDS ? lxy[cl.flidx[k]] : cl.xy[cl.idx[k]];
+                ok &= mirror_entry_f<LIMITER, POW, FIRST>(Q.x - P.x, Q.y - P.y, N, qp, gp, bp,
+                                                          w, Ginf, gm1inv, vk, R);
+            }
+        }
+    }
+    if (!ok) report_pt(cl, err, p, kErrPositivity);
+}
+
 }  // namespace
 
 template <bool LIMITER, int POW, bool FIRST, bool KOBC>
@@ -1495,7 +1656,7 @@ k_flux_mixed(
     const float4 *__restrict__ q32, const float4 *__restrict__ g32,
     const float4 *__restrict__ qmm32, double *__restrict__ U, double *__restrict__ Un,
     double *__restrict__ dt, double2 *__restrict__ qnext, float4 *__restrict__ q32next,
-    double *__restrict__ Rout, int *err) {
+    double *__restrict__ Rout, ErrWord *err) {
     // slot record (float4): q 0, g 1..2, bounds 3..4 (first order: q only);
     // positions after cap records
     constexpr int kRec = FIRST ? 1 : (LIMITER ? 5 : 3);
@@ -1543,92 +1704,13 @@ k_flux_mixed(
     }
     double2 N = make_double2(0.0, 0.0);
     if (live) {
-        const float gm1inv = (float)fp.gm1inv;
-        const float vk = (float)fp.venkat_k;
         N = cl.nrm[p];
-        float qp[4], gp[8], bp[8];
-        double w[8];
-        double2 P;
-        if (in_lds) {
-            const float4 *r = ldsf + kRec * j;
-            unpack(r[0], qp);
-            if (!FIRST) {
-                unpack(r[1], gp);
-                unpack(r[2], gp + 4);
-            }
-            if (LIMITER) {
-                unpack(r[3], bp);
-                unpack(r[4], bp + 4);
-            }
-            P = lxy[j];
-        } else {
-            unpack(q32[p], qp);
-            if (!FIRST) {
-                unpack(g32[2 * p], gp);
-                unpack(g32[2 * p + 1], gp + 4);
-            }
-            if (LIMITER) {
-                unpack(qmm32[2 * p], bp);
-                unpack(qmm32[2 * p + 1], bp + 4);
-            }
-            P = cl.xy[p];
-        }
-#pragma unroll
-        for (int m = 0; m < 8; ++m) w[m] = cl.lsw[8 * p + m];
-        uint8_t fmask = (kd == kWall) ? uint8_t(~kNPlus) : uint8_t(0xff);
-        if constexpr (KOBC) {
-            if (kd == kOuter) fmask &= uint8_t(~kNMinus);
-        }
-        const int k1 = cl.ptr[p + 1];
-        bool ok = true;
-#pragma unroll 2
-        for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
-            const uint8_t f = cl.flag[k] & fmask;
-            if (f == 0) continue;
-            float qi[4], gi[8], bi[8];
-            double2 Q;
-            if (in_lds) {
-                const int s = cl.flidx[k];
-                const float4 *r = ldsf + kRec * s;
-                unpack(r[0], qi);
-                if (!FIRST) {
-                    unpack(r[1], gi);
-                    unpack(r[2], gi + 4);
-                }
-                if (LIMITER) {
-                    unpack(r[3], bi);
-                    unpack(r[4], bi + 4);
-                }
-                Q = lxy[s];
-            } else {
-                const int i = cl.idx[k];
-                unpack(q32[i], qi);
-                if (!FIRST) {
-                    unpack(g32[2 * i], gi);
-                    unpack(g32[2 * i + 1], gi + 4);
-                }
-                if (LIMITER) {
-                    unpack(qmm32[2 * i], bi);
-                    unpack(qmm32[2 * i + 1], bi + 4);
-                }
-                Q = cl.xy[i];
-            }
-            ok &= flux_entry_f<LIMITER, POW, FIRST>(f, Q.x - P.x, Q.y - P.y, N, qi, gi, bi, qp, gp, bp,
-                                             w, gm1inv, vk, R);
-        }
-        if constexpr (KOBC) {
-            if (kd == kOuter) {
-                float Ginf[4];
-                ok &= freestream_flux_f<POW>(cl.uinf + 4 * cl.case_of[p], N, fp, Ginf);
-                for (int k = cl.ptr[p] + sub; k < k1; k += kFluxLanes) {
-                    if (!(cl.flag[k] & kNPlus)) continue;
-                    const double2 Q = in_lds ? lxy[cl.flidx[k]] : cl.xy[cl.idx[k]];
-                    ok &= mirror_entry_f<LIMITER, POW, FIRST>(Q.x - P.x, Q.y - P.y, N, qp, gp, bp,
-                                                              w, Ginf, gm1inv, vk, R);
-                }
-            }
-        }
-        if (!ok) report(err, p, kErrPositivity);
+        if (in_lds)
+            flux_point_f<true, LIMITER, POW, FIRST, KOBC>(cl, fp, ldsf, lxy, j, p, sub, kd, N,
+                                                          q32, g32, qmm32, R, err);
+        else
+            flux_point_f<false, LIMITER, POW, FIRST, KOBC>(cl, fp, ldsf, lxy, j, p, sub, kd, N,
+                                                           q32, g32, qmm32, R, err);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) R[r] = lane_group_sum(R[r]);
@@ -1657,7 +1739,7 @@ hipError_t launch_flux_mixed(hipStream_t st, const DevCloud &c, const FlowParams
                              int lds_budget, const double2 *q, const float4 *q32,
                              const float4 *g32, const float4 *qmm32, double *U, double *Un,
                              double *dt, double2 *qnext, float4 *q32next, double *Rout,
-                             int *err) {
+                             ErrWord *err) {
     const bool first = fp.order == 1;
     const int rec = ((first ? 1 : fp.limiter ? 5 : 3) + 1) * (int)sizeof(float4);
     const int cap = lds_cap(c, lds_budget, rec);
@@ -1716,10 +1798,12 @@ __global__ void __launch_bounds__(kBlock) k_res_cases(int ncase, const int *__re
                                                       const double *__restrict__ part,
                                                       const double *__restrict__ inv_nupd,
                                                       int *ctr, int cap,
-                                                      double *__restrict__ hist) {
+                                                      double *__restrict__ hist, Retire rt) {
     __shared__ double red[kBlock / 64][4];
+    __shared__ double nv[4];
     const int row = *ctr;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const double drop = rt.on ? *rt.drop : 0.0;
     for (int cs = 0; cs < ncase; ++cs) {
         double acc[4] = {0, 0, 0, 0};
         for (int j = chunk_ptr[cs] + threadIdx.x; j < chunk_ptr[cs + 1]; j += kBlock) {
@@ -1732,23 +1816,56 @@ __global__ void __launch_bounds__(kBlock) k_res_cases(int ncase, const int *__re
             if (lane == 0) red[wv][c] = t;
         }
         __syncthreads();
-        if (threadIdx.x < 4 && row < cap) {
+        if (threadIdx.x < 4) {
             double t = 0.0;
 #pragma unroll
             for (int j = 0; j < kBlock / 64; ++j) t += red[j][threadIdx.x];
-            hist[((size_t)row * ncase + cs) * 4 + threadIdx.x] = sqrt(t * inv_nupd[cs]);
+            const double v = sqrt(t * inv_nupd[cs]);
+            if (row < cap) hist[((size_t)row * ncase + cs) * 4 + threadIdx.x] = v;
+            nv[threadIdx.x] = v;
         }
         __syncthreads();
+        // retirement: this iteration's norms are those of the state it
+        // started from, and the state it leaves is the one a case keeps
+        if (rt.on && threadIdx.x == 0 && rt.active[cs]) {
+            rt.iters[cs] += 1;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rt.last[4 * cs + c] = nv[c];
+            double ref = rt.ref[cs];
+            if (ref < 0.0) ref = rt.ref[cs] = nv[0];
+            if (rt.case_err[cs] != kErrClear || nv[0] <= drop * ref ||
+                nv[0] > kDiverged * ref || !(nv[0] == nv[0]))
+                rt.active[cs] = 0;
+        }
     }
     if (threadIdx.x == 0) *ctr = row + 1;
 }
 
+// tile t is skipped by every tiled sweep when no case it holds is active
+__global__ void __launch_bounds__(kBlock) k_tile_active(int n, int ntile,
+                                                        const int *__restrict__ case_of,
+                                                        const uint8_t *__restrict__ case_active,
+                                                        uint8_t *__restrict__ tile_active) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= ntile) return;
+    const int b = t * kFluxTile, e = min(n, b + kFluxTile) - 1;
+    uint8_t any = 0;
+    for (int c = case_of[b]; c <= case_of[e]; ++c) any |= case_active[c];
+    tile_active[t] = any;
+}
+
 hipError_t launch_resnorm(hipStream_t st, const double *R, int n, int nchunk, const int *chunk_beg,
                           double *part, int ncase, const int *chunk_ptr, const double *inv_nupd,
-                          int *ctr, int cap, double *hist) {
+                          int *ctr, int cap, double *hist, const Retire &rt,
+                          const int *case_of, uint8_t *tile_active) {
     hipLaunchKernelGGL(k_res_chunks, dim3(nchunk), dim3(kBlock), 0, st, R, n, chunk_beg, part);
     hipLaunchKernelGGL(k_res_cases, dim3(1), dim3(kBlock), 0, st, ncase, chunk_ptr, part,
-                       inv_nupd, ctr, cap, hist);
+                       inv_nupd, ctr, cap, hist, rt);
+    if (rt.on) {
+        const int ntile = num_flux_tiles(n);
+        hipLaunchKernelGGL(k_tile_active, dim3((ntile + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+                           n, ntile, case_of, rt.active, tile_active);
+    }
     return hipGetLastError();
 }
 

@@ -95,9 +95,18 @@ struct ql_solver {
     int nchunk = 0;
     int zero = 0;  // source of the history-row counter reset
     int reshist_cap = 0;
-    int *errw = nullptr;
-    int *errw_outer = nullptr;  // singular split stencils of outer points (set-up)
-    int err_init[2] = {INT_MAX, 0};  // source of the error-word reset copies
+    ErrWord *errw = nullptr;
+    ErrWord *errw_outer = nullptr;  // singular split stencils of outer points (set-up)
+    ErrWord err_clear = kErrClear;  // source of the error-word reset copies
+    // batched runs: per-case error words and the device retirement state
+    ErrWord *case_err = nullptr;
+    std::vector<ErrWord> case_err_clear;  // [ncase] source of the reset copies
+    double *bt_ref = nullptr, *bt_last = nullptr, *bt_drop = nullptr;
+    int *bt_iters = nullptr;
+    bool retire_on = false;  // iterations enqueued now retire cases on the device
+    // ql_step without a history: the iterations' status and last norms are
+    // collected by the next call (rows of history written)
+    int step_pending = 0;
     int qcur = 0, gfin = 0;
     std::vector<double> last_res;  // [ncase][4]
     std::vector<int32_t> case_status;  // per case, of the last ql_batch_run
@@ -161,7 +170,9 @@ void free_cloud(ql_solver *s) {
     dfree(s->case_of); dfree(s->chunk_beg); dfree(s->chunk_ptr); dfree(s->ctr);
     dfree(s->dwall_lo); dfree(s->wctr); dfree(s->wsel); dfree(s->wres);
     dfree(s->case_active); dfree(s->tile_active); dfree(s->uinf); dfree(s->part);
-    dfree(s->inv_nupd);
+    dfree(s->inv_nupd); dfree(s->case_err); dfree(s->bt_ref); dfree(s->bt_last);
+    dfree(s->bt_drop); dfree(s->bt_iters);
+    s->step_pending = 0;
     if (s->graph) (void)hipGraphExecDestroy(s->graph);
     s->graph = nullptr;
     s->graph_qcur = -1;
@@ -353,6 +364,7 @@ DevCloud dev_cloud(const ql_solver *s) {
     c.case_active = s->case_active;
     c.tile_active = s->tile_active;
     c.uinf = s->uinf;
+    c.case_err = s->case_err;
     return c;
 }
 
@@ -400,16 +412,23 @@ int check_params(ql_solver *s, const ql_params *p) {
 }
 
 int reset_err(ql_solver *s) {
-    HIPCHK(s, hipMemcpyAsync(s->errw, s->err_init, sizeof s->err_init, hipMemcpyHostToDevice,
+    HIPCHK(s, hipMemcpyAsync(s->errw, &s->err_clear, sizeof(ErrWord), hipMemcpyHostToDevice,
                              s->stream));
     return QL_OK;
 }
 
-// Status of a device error word (library-order point e[0], code e[1]).
-static int err_status(ql_solver *s, const int e[2], const char *what) {
-    if (e[1] == kErrNone) return QL_OK;
-    const int up = (e[0] >= 0 && e[0] < s->n) ? s->perm[e[0]] : -1;
-    switch (e[1]) {
+int reset_case_err(ql_solver *s) {
+    HIPCHK(s, hipMemcpyAsync(s->case_err, s->case_err_clear.data(), sizeof(ErrWord) * s->ncase,
+                             hipMemcpyHostToDevice, s->stream));
+    return QL_OK;
+}
+
+// Status of a device error word (library-order point and code).
+static int err_status(ql_solver *s, ErrWord w, const char *what) {
+    const int code = err_code(w), pt = err_point(w);
+    if (code == kErrNone) return QL_OK;
+    const int up = (pt >= 0 && pt < s->n) ? s->perm[pt] : -1;
+    switch (code) {
     case kErrSingular:
         return fail(s, QL_ESINGULAR, "%s: singular least-squares stencil at point %d", what, up);
     case kErrNonFinite:
@@ -422,24 +441,18 @@ static int err_status(ql_solver *s, const int e[2], const char *what) {
 }
 
 // Synchronise and read the device error word.
-static int read_err(ql_solver *s, int e[2]) {
-    HIPCHK(s, hipMemcpyAsync(e, s->errw, 2 * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+static int read_err(ql_solver *s, ErrWord *w) {
+    HIPCHK(s, hipMemcpyAsync(w, s->errw, sizeof(ErrWord), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
     return QL_OK;
 }
 
 // Synchronise and turn the device error word into a status.
 int sync_and_check(ql_solver *s, const char *what) {
-    int e[2];
-    int st = read_err(s, e);
+    ErrWord w = kErrClear;
+    int st = read_err(s, &w);
     if (st) return st;
-    return err_status(s, e, what);
-}
-
-// The case holding library-order point p (cases keep their point ranges).
-static int case_of_point(const ql_solver *s, int p) {
-    const auto it = std::upper_bound(s->case_lo.begin(), s->case_lo.end(), p);
-    return (int)(it - s->case_lo.begin()) - 1;
+    return err_status(s, w, what);
 }
 
 hipEvent_t take_event(ql_solver *s) {
@@ -582,9 +595,11 @@ int enqueue_iteration(ql_solver *s, const DevCloud &c, const FlowParams &fp, int
         s->qcur = 1 - s->qcur;
     }
     Timer t(s, 3);
+    const Retire rt{s->retire_on ? 1 : 0, s->bt_drop, s->bt_ref, s->bt_iters, s->bt_last,
+                    s->case_active, s->case_err};
     HIPCHK(s, launch_resnorm(s->stream, s->R, s->n, s->nchunk, s->chunk_beg, s->part, s->ncase,
                              s->chunk_ptr, s->inv_nupd + (fp.kobc ? s->ncase : 0), s->ctr,
-                             hist_cap, s->reshist));
+                             hist_cap, s->reshist, rt, s->case_of, s->tile_active));
     t.done();
     return QL_OK;
 }
@@ -641,9 +656,29 @@ void drop_graph(ql_solver *s) {
     s->graph_qcur = -1;
 }
 
+// Collect the outcome of iterations that ql_step enqueued without a
+// history: their last residual norms and the error word (one
+// synchronisation).  A failure is returned to the call that collects it.
+int settle(ql_solver *s) {
+    if (!s->step_pending) return QL_OK;
+    const size_t row = (size_t)s->step_pending - 1;
+    s->step_pending = 0;
+    (void)hipSetDevice(s->device);
+    std::vector<double> last((size_t)4 * s->ncase);
+    HIPCHK(s, hipMemcpyAsync(last.data(), s->reshist + row * s->ncase * 4,
+                             sizeof(double) * last.size(), hipMemcpyDeviceToHost, s->stream));
+    const int st = sync_and_check(s, "step");
+    harvest_timing(s);
+    if (st) return st;
+    s->last_res = last;
+    s->has_res = true;
+    return QL_OK;
+}
+
 int ensure_ready(ql_solver *s, bool need_state) {
     if (!s) return QL_EINVAL;
     if (s->poisoned) return QL_EDEVICE;
+    if (int st = settle(s)) return st;
     if (!s->has_cloud) return fail(s, QL_ESTATE, "no cloud uploaded");
     if (need_state && !s->has_state) return fail(s, QL_ESTATE, "no flow state set");
     return QL_OK;
@@ -718,6 +753,8 @@ int ql_destroy(ql_solver *s) {
 
 const char *ql_last_error(const ql_solver *s) { return s ? s->err.c_str() : "null solver"; }
 
+static int upload_freestream(ql_solver *s);
+
 int ql_set_params(ql_solver *s, const ql_params *p) {
     if (!s) return QL_EINVAL;
     if (s->poisoned) return QL_EDEVICE;
@@ -728,8 +765,14 @@ int ql_set_params(ql_solver *s, const ql_params *p) {
     for (int k = 0; k < 2; ++k)
         if (s->has_cloud && p->flux_split && !s->Rpart[k])
             HIPCHK(s, dalloc(&s->Rpart[k], (size_t)4 * s->n));
+    if (s->has_cloud) {
+        (void)hipSetDevice(s->device);
+        return upload_freestream(s);
+    }
     return QL_OK;
 }
+
+static int upload_freestream(ql_solver *s);
 
 static int upload_impl(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int64_t n64,
                        const double *x, const double *y, const double *nx, const double *ny,
@@ -865,8 +908,11 @@ static int upload_impl(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int
     HIPCHK(s, dalloc(&s->q32[0], n)); HIPCHK(s, dalloc(&s->q32[1], n));
     HIPCHK(s, dalloc(&s->g32, (size_t)2 * n)); HIPCHK(s, dalloc(&s->qmm32, (size_t)2 * n));
     HIPCHK(s, dalloc(&s->fscratch, (size_t)3 * std::max<size_t>(hwall.size(), 1)));
-    HIPCHK(s, dalloc(&s->fout, 2)); HIPCHK(s, dalloc(&s->errw, 2));
-    HIPCHK(s, dalloc(&s->errw_outer, 2));
+    HIPCHK(s, dalloc(&s->fout, 2)); HIPCHK(s, dalloc(&s->errw, 1));
+    HIPCHK(s, dalloc(&s->errw_outer, 1)); HIPCHK(s, dalloc(&s->case_err, ncase));
+    HIPCHK(s, dalloc(&s->bt_ref, ncase)); HIPCHK(s, dalloc(&s->bt_last, (size_t)4 * ncase));
+    HIPCHK(s, dalloc(&s->bt_drop, 1)); HIPCHK(s, dalloc(&s->bt_iters, ncase));
+    s->case_err_clear.assign(ncase, kErrClear);
     HIPCHK(s, dalloc(&s->case_of, n)); HIPCHK(s, dalloc(&s->uinf, (size_t)4 * ncase));
     HIPCHK(s, dalloc(&s->case_active, ncase)); HIPCHK(s, dalloc(&s->tile_active, ntile));
     HIPCHK(s, dalloc(&s->chunk_beg, nchunk + 1)); HIPCHK(s, dalloc(&s->chunk_ptr, ncase + 1));
@@ -922,20 +968,23 @@ static int upload_impl(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int
     s->eperm.swap(eperm);
 
     int rc = reset_err(s);
+    if (!rc) rc = reset_case_err(s);
     if (rc) return rc;
-    HIPCHK(s, hipMemcpyAsync(s->errw_outer, s->err_init, sizeof s->err_init,
+    HIPCHK(s, hipMemcpyAsync(s->errw_outer, &s->err_clear, sizeof(ErrWord),
                              hipMemcpyHostToDevice, st));
     HIPCHK(s, launch_setup(st, n, s->xy, s->nrm, s->kind, s->ptr, s->idx, s->flag,
                            nbr_flag ? 0 : 1, s->lsw, s->lsi, s->dmin, s->errw, s->errw_outer));
-    int eo[2] = {INT_MAX, 0};
-    HIPCHK(s, hipMemcpyAsync(eo, s->errw_outer, sizeof eo, hipMemcpyDeviceToHost, st));
+    ErrWord eo = kErrClear;
+    HIPCHK(s, hipMemcpyAsync(&eo, s->errw_outer, sizeof eo, hipMemcpyDeviceToHost, st));
     // host buffers above must outlive the asynchronous copies
     rc = sync_and_check(s, "upload");
-    s->outer_bad = (eo[1] != kErrNone && eo[0] >= 0 && eo[0] < n) ? s->perm[eo[0]] : -1;
+    const int eop = err_point(eo);
+    s->outer_bad = (err_code(eo) != kErrNone && eop >= 0 && eop < n) ? s->perm[eop] : -1;
     if (!rc && s->prm.outer_bc == 1 && s->outer_bad >= 0)
         rc = fail(s, QL_ESINGULAR,
                   "upload: kinetic outer condition: singular split stencil at outer point %d",
                   s->outer_bad);
+    if (!rc) rc = upload_freestream(s);
     if (rc) {
         const std::string msg = s->err;
         free_cloud(s);
@@ -972,7 +1021,14 @@ int ql_cloud_size(const ql_solver *s, int64_t *n, int64_t *nnz) {
 }
 
 // Conserved freestream of every case into s->uinf (rho = 1, p = 1/gamma).
+// Conserved freestream of every case into s->uinf (the one-case form takes
+// the Mach number and incidence of ql_set_params).  The kinetic outer
+// condition reads it at every flux evaluation, whatever set the state.
 static int upload_freestream(ql_solver *s) {
+    if (s->ncase == 1) {
+        s->case_mach[0] = s->prm.mach;
+        s->case_alpha[0] = s->prm.alpha_deg;
+    }
     s->uinf_host.assign((size_t)4 * s->ncase, 0.0);
     for (int c = 0; c < s->ncase; ++c) {
         const double a = s->case_alpha[c] * M_PI / 180.0;
@@ -986,6 +1042,8 @@ static int upload_freestream(ql_solver *s) {
     }
     HIPCHK(s, hipMemcpyAsync(s->uinf, s->uinf_host.data(), sizeof(double) * s->uinf_host.size(),
                              hipMemcpyHostToDevice, s->stream));
+    // the host copy is rewritten by the next call: let this one complete
+    HIPCHK(s, hipStreamSynchronize(s->stream));
     return QL_OK;
 }
 
@@ -993,10 +1051,6 @@ int ql_init_freestream(ql_solver *s) {
     int st = ensure_ready(s, false);
     if (st) return st;
     (void)hipSetDevice(s->device);
-    if (s->ncase == 1) {  // the one-case API follows ql_set_params
-        s->case_mach[0] = s->prm.mach;
-        s->case_alpha[0] = s->prm.alpha_deg;
-    }
     if ((st = upload_freestream(s))) return st;
     HIPCHK(s, launch_freestream(s->stream, s->n, s->nrm, s->kind, s->case_of, s->uinf, s->U));
     st = prep_state(s);
@@ -1057,6 +1111,12 @@ int ql_step(ql_solver *s, int32_t n_iter, double *res_hist) {
     if ((st = reset_counter(s))) return st;
     for (int it = 0; it < n_iter; ++it)
         if ((st = enqueue_iteration(s, c, fp, s->reshist_cap / s->ncase))) return st;
+    s->has_eval = false;
+    if (!res_hist) {  // no synchronisation: the next call collects the outcome
+        s->step_pending = n_iter;
+        s->has_res = false;
+        return QL_OK;
+    }
     const size_t rows = (size_t)n_iter * s->ncase * 4;
     std::vector<double> hist(rows);
     HIPCHK(s, hipMemcpyAsync(hist.data(), s->reshist, sizeof(double) * rows, hipMemcpyDeviceToHost,
@@ -1074,6 +1134,9 @@ int ql_step(ql_solver *s, int32_t n_iter, double *res_hist) {
 
 int ql_residual_norm(const ql_solver *s, double out[4]) {
     if (!s || !out) return QL_EINVAL;
+    // collecting a pending step's norms changes no observable state but the
+    // cached norms themselves
+    if (int st = settle(const_cast<ql_solver *>(s))) return st;
     if (!s->has_res) return QL_ESTATE;
     std::memcpy(out, s->last_res.data(), sizeof(double) * 4);
     return QL_OK;
@@ -1204,9 +1267,10 @@ static int warm_eval(ql_solver *s, const DevCloud &c, const FlowParams &fp) {
     if (st) return st;
     if ((st = run_gradients(s, c, fp.limiter != 0, false))) return st;
     if ((st = launch_stage(s, c, fp, 0, s->R))) return st;
+    const Retire off{0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     HIPCHK(s, launch_resnorm(s->stream, s->R, s->n, s->nchunk, s->chunk_beg, s->part, s->ncase,
                              s->chunk_ptr, s->inv_nupd + (fp.kobc ? s->ncase : 0), s->wctr, 2,
-                             s->wres));
+                             s->wres, off, s->case_of, s->tile_active));
     return QL_OK;
 }
 
@@ -1236,10 +1300,6 @@ int ql_warm_start(ql_solver *s, ql_mlp *m, const float *X, const float *out_scal
     if (!(rel_floor > 0.0 && rel_floor < 1.0)) return fail(s, QL_EINVAL, "floor must lie in (0, 1)");
     (void)hipSetDevice(s->device);
     const int n = s->n, nc = s->ncase;
-    if (s->ncase == 1) {
-        s->case_mach[0] = s->prm.mach;
-        s->case_alpha[0] = s->prm.alpha_deg;
-    }
     // network output (caller order, FP32 [n][4]) into the residual buffer
     float *Y = reinterpret_cast<float *>(s->R);
     HIPCHK(s, hipStreamSynchronize(s->stream));
@@ -1259,19 +1319,16 @@ int ql_warm_start(ql_solver *s, ql_mlp *m, const float *X, const float *out_scal
     const FlowParams fp = flow_params(s);
     HIPCHK(s, hipMemcpyAsync(s->wctr, &s->zero, sizeof(int), hipMemcpyHostToDevice, s->stream));
     // warm candidate: its stage-1 residual norms (row 0); a positivity or
-    // finiteness failure rejects the failing point's case
+    // finiteness failure rejects every case in which a point failed
     HIPCHK(s, hipMemcpyAsync(s->U, s->tmp, sizeof(double) * 4 * n, hipMemcpyDeviceToDevice,
                              s->stream));
+    if ((st = reset_case_err(s))) return st;
     if ((st = warm_eval(s, c, fp))) return st;
-    int ew[2];
-    HIPCHK(s, hipMemcpyAsync(ew, s->errw, sizeof ew, hipMemcpyDeviceToHost, s->stream));
+    std::vector<ErrWord> cew(nc);
+    HIPCHK(s, hipMemcpyAsync(cew.data(), s->case_err, sizeof(ErrWord) * nc, hipMemcpyDeviceToHost,
+                             s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
-    int bad_case = -1;
-    if (ew[1] != kErrNone && ew[0] >= 0 && ew[0] < n) {
-        const int up = s->perm[ew[0]];
-        for (int k = 0; k < nc; ++k)
-            if (up >= s->case_lo[k] && up < s->case_lo[k + 1]) bad_case = k;
-    }
+    if ((st = reset_case_err(s))) return st;
     // cold start: freestream (row 1); failures here are errors
     HIPCHK(s, launch_freestream(s->stream, n, s->nrm, s->kind, s->case_of, s->uinf, s->U));
     if ((st = warm_eval(s, c, fp))) return st;
@@ -1282,7 +1339,7 @@ int ql_warm_start(ql_solver *s, ql_mlp *m, const float *X, const float *out_scal
     std::vector<uint8_t> sel(nc, 0);
     for (int k = 0; k < nc; ++k) {
         const double w = rows[4 * k], cold = rows[(size_t)4 * nc + 4 * k];
-        sel[k] = (k != bad_case && std::isfinite(w) && w <= cold) ? 1 : 0;
+        sel[k] = (err_code(cew[k]) == kErrNone && std::isfinite(w) && w <= cold) ? 1 : 0;
         if (res_warm) std::copy(&rows[4 * k], &rows[4 * k] + 4, res_warm + 4 * k);
         if (res_cold) std::copy(&rows[(size_t)4 * nc + 4 * k], &rows[(size_t)4 * nc + 4 * k] + 4,
                                 res_cold + 4 * k);
@@ -1479,102 +1536,87 @@ int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_ever
     const int nc = s->ncase, ntile = num_flux_tiles(s->n);
     const int block = std::min(check_every, std::max(max_iter, 1));
     if ((st = ensure_history(s, block))) return st;
+    // device retirement state: every case active, no reference yet (or the
+    // caller's), no iterations, no failure
     std::vector<uint8_t> active(nc, 1), tile(ntile, 1);
     std::vector<double> ref(nc, -1.0), last((size_t)4 * nc, 0.0);
     if (ref_res) ref.assign(ref_res, ref_res + nc);
     std::vector<int> iters(nc, 0);
+    std::vector<ErrWord> cerr(nc, kErrClear);
     std::vector<int32_t> status(nc, QL_OK);
+    const double drop_h = drop;
     HIPCHK(s, hipMemcpyAsync(s->case_active, active.data(), nc, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemcpyAsync(s->tile_active, tile.data(), ntile, hipMemcpyHostToDevice, s->stream));
-    if ((st = reset_err(s))) return st;
+    HIPCHK(s, hipMemcpyAsync(s->bt_ref, ref.data(), sizeof(double) * nc, hipMemcpyHostToDevice,
+                             s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->bt_last, last.data(), sizeof(double) * 4 * nc,
+                             hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->bt_iters, iters.data(), sizeof(int) * nc, hipMemcpyHostToDevice,
+                             s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->bt_drop, &drop_h, sizeof(double), hipMemcpyHostToDevice,
+                             s->stream));
+    if ((st = reset_err(s)) || (st = reset_case_err(s))) return st;
     const DevCloud c = dev_cloud(s);
     const FlowParams fp = flow_params(s);
-    std::vector<double> hist((size_t)block * nc * 4);
+    // the iterations enqueued below retire cases on the device at the
+    // iteration they converge, diverge or fail; the host only looks between
+    // windows of check_every iterations, to stop once no case is active
+    s->retire_on = true;
     int done = 0, nactive = nc;
     while (done < max_iter && nactive > 0) {
         const int k = std::min(block, max_iter - done);
-        if ((st = reset_counter(s))) return st;
+        if ((st = reset_counter(s))) break;
         if (graph) {
-            if ((st = capture_iteration(s))) return st;
-            for (int it = 0; it < k; ++it) HIPCHK(s, hipGraphLaunch(s->graph, s->stream));
+            if ((st = capture_iteration(s))) break;
+            for (int it = 0; it < k && !st; ++it)
+                if (hipGraphLaunch(s->graph, s->stream) != hipSuccess)
+                    st = fail(s, QL_EDEVICE, "graph launch failed");
+            if (st) break;
         } else {
-            for (int it = 0; it < k; ++it)
-                if ((st = enqueue_iteration(s, c, fp, block))) return st;
+            for (int it = 0; it < k && !st; ++it) st = enqueue_iteration(s, c, fp, block);
+            if (st) break;
         }
-        HIPCHK(s, hipMemcpyAsync(hist.data(), s->reshist, sizeof(double) * k * nc * 4,
-                                 hipMemcpyDeviceToHost, s->stream));
-        int e[2];
-        if ((st = read_err(s, e))) return st;
+        HIPCHK(s, hipMemcpyAsync(active.data(), s->case_active, nc, hipMemcpyDeviceToHost,
+                                 s->stream));
+        HIPCHK(s, hipStreamSynchronize(s->stream));
         harvest_timing(s);
-        bool changed = false;
-        if (e[1] != kErrNone) {
-            // a case whose state failed (positivity or a non-finite value)
-            // retires with that status; the others go on
-            const int fc = (e[0] >= 0 && e[0] < s->n) ? case_of_point(s, e[0]) : -1;
-            if ((e[1] != kErrPositivity && e[1] != kErrNonFinite) || fc < 0)
-                return err_status(s, e, "batch_run");
-            if (active[fc]) {
-                status[fc] = (e[1] == kErrPositivity) ? QL_EPOSITIVITY : QL_ENONFINITE;
-                iters[fc] += k;
-                active[fc] = 0;
-                --nactive;
-                changed = true;
-            }
-            if ((st = reset_err(s))) return st;
-        }
-        for (int cs = 0; cs < nc; ++cs) {
-            if (!active[cs]) continue;
-            for (int r = 0; r < k; ++r) {
-                const double *h = &hist[((size_t)r * nc + cs) * 4];
-                iters[cs] += 1;
-                std::memcpy(&last[4 * cs], h, sizeof(double) * 4);
-                if (ref[cs] < 0.0) ref[cs] = h[0];
-                if (h[0] <= drop * ref[cs]) {
-                    active[cs] = 0;
-                    --nactive;
-                    changed = true;
-                    break;
-                }
-            }
-        }
+        nactive = (int)std::count(active.begin(), active.end(), (uint8_t)1);
         done += k;
-        if (changed && nactive > 0) {
-            // freeze retired cases; skip tiles that hold only retired points
-            for (int t = 0; t < ntile; ++t) {
-                const int b = t * kFluxTile, e = std::min(s->n, b + kFluxTile) - 1;
-                int c0 = 0;
-                while (s->case_lo[c0 + 1] <= b) ++c0;
-                int c1 = c0;
-                while (s->case_lo[c1 + 1] <= e) ++c1;
-                uint8_t any = 0;
-                for (int cs = c0; cs <= c1; ++cs) any |= active[cs];
-                tile[t] = any;
-            }
-            HIPCHK(s, hipMemcpyAsync(s->case_active, active.data(), nc, hipMemcpyHostToDevice,
-                                     s->stream));
-            HIPCHK(s, hipMemcpyAsync(s->tile_active, tile.data(), ntile, hipMemcpyHostToDevice,
-                                     s->stream));
-            HIPCHK(s, hipStreamSynchronize(s->stream));
-        }
+    }
+    s->retire_on = false;
+    if (st) return st;
+    HIPCHK(s, hipMemcpyAsync(iters.data(), s->bt_iters, sizeof(int) * nc, hipMemcpyDeviceToHost,
+                             s->stream));
+    HIPCHK(s, hipMemcpyAsync(last.data(), s->bt_last, sizeof(double) * 4 * nc,
+                             hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(ref.data(), s->bt_ref, sizeof(double) * nc, hipMemcpyDeviceToHost,
+                             s->stream));
+    HIPCHK(s, hipMemcpyAsync(cerr.data(), s->case_err, sizeof(ErrWord) * nc,
+                             hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    for (int cs = 0; cs < nc; ++cs) {
+        const int code = err_code(cerr[cs]);
+        if (code == kErrPositivity) status[cs] = QL_EPOSITIVITY;
+        else if (code == kErrNonFinite) status[cs] = QL_ENONFINITE;
+        else if (code != kErrNone) return err_status(s, cerr[cs], "batch_run");
+        else if (iters[cs] > 0 && !(last[4 * cs] <= kDiverged * ref[cs]))
+            status[cs] = QL_EDIVERGED;
     }
     // leave every case active for later calls, and rebuild the start-of-
-    // iteration data (q, time step, Un) from U: skipped tiles did not keep
-    // the q buffers of retired cases current
+    // iteration data (q, time step, Un) from U: retired cases' q buffers were
+    // not kept current.  Only a case that failed may fail here.
     std::fill(active.begin(), active.end(), 1);
     std::fill(tile.begin(), tile.end(), 1);
     HIPCHK(s, hipMemcpyAsync(s->case_active, active.data(), nc, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemcpyAsync(s->tile_active, tile.data(), ntile, hipMemcpyHostToDevice, s->stream));
-    if ((st = prep_state(s))) return st;
-    {
-        // a failed case's state may still fail here; only failed cases can
-        int e[2];
-        if ((st = read_err(s, e))) return st;
-        if (e[1] != kErrNone) {
-            const int fc = (e[0] >= 0 && e[0] < s->n) ? case_of_point(s, e[0]) : -1;
-            if (fc < 0 || status[fc] == QL_OK) return err_status(s, e, "batch_run");
-            if ((st = reset_err(s))) return st;
-        }
-    }
+    if ((st = reset_case_err(s)) || (st = prep_state(s))) return st;
+    HIPCHK(s, hipMemcpyAsync(cerr.data(), s->case_err, sizeof(ErrWord) * nc,
+                             hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    for (int cs = 0; cs < nc; ++cs)
+        if (err_code(cerr[cs]) != kErrNone && status[cs] == QL_OK)
+            return err_status(s, cerr[cs], "batch_run");
+    if ((st = reset_err(s)) || (st = reset_case_err(s))) return st;
     s->has_eval = false;
     s->case_status = status;
     s->last_res = last;
@@ -1596,6 +1638,7 @@ int ql_set_timing(ql_solver *s, int32_t enable) {
 
 int ql_kernel_time(const ql_solver *s, int32_t which, double *total_ms, int64_t *count) {
     if (!s || which < 0 || which > 3) return QL_EINVAL;
+    if (int st = settle(const_cast<ql_solver *>(s))) return st;
     if (total_ms) *total_ms = s->tsum[which];
     if (count) *count = s->tcnt[which];
     return QL_OK;

@@ -549,6 +549,9 @@ class Solver:
     def step(self, n_iter, want_history=True):
         return ql_step(self.h, n_iter, want_history)
 
+    def residual_norm(self):
+        return ql_residual_norm(self.h)
+
     def fetch_state(self, out=None):
         return ql_fetch_state(self.h, out)
 

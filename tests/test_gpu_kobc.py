@@ -88,8 +88,14 @@ def test_run_parity_c1_100(ql, limiter):
     _say(f"  state err {err}")
     assert np.all(err <= 1e-11), err
     outer = c.kind == KIND_OUTER
-    # the outer layer moved away from the freestream
-    assert np.abs(Uo[:, outer] - o.freestream()[:, outer]).max() > 1e-8
+    # the outer layer moved away from the freestream (held points would not
+    # move at all; after 100 iterations the disturbance reaching 15 chords is
+    # about 1e-9), and the GPU reproduces that motion closely
+    moved = np.abs(Uo[:, outer] - o.freestream()[:, outer]).max()
+    _say(f"  outer layer motion {moved:.3e}, GPU error there "
+         f"{np.abs(Ug[:, outer] - Uo[:, outer]).max():.3e}")
+    assert moved > 1e-10
+    assert np.abs(Ug[:, outer] - Uo[:, outer]).max() <= 0.05 * moved
     assert np.all(normwise_rel(hist_g.T, hist_o.T) <= 1e-10)
     clg, cdg = s.forces()
     clo, cdo = o.forces(Uo)
