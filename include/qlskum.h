@@ -178,6 +178,19 @@ int ql_set_state(ql_solver *s, const double *U, int32_t mem, int32_t project_wal
  * point and its own code; the state is then undefined), QL_EDEVICE. */
 int ql_step(ql_solver *s, int32_t n_iter, double *res_hist);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, serving loops, harnesses that forbid hipMalloc): ql_step with
+ * the residual history staged in a fixed device array of the library
+ * instead of a buffer the solver grows, and no timing events.  Same
+ * kernels, same results as ql_step bit for bit.  The array holds 65536
+ * doubles per GPU (allocated once per process and device, never freed):
+ * n_iter x ncase x 4 must not exceed it, else QL_EINVAL.  Every call on a
+ * GPU shares that GPU's array, so calls that overlap on one GPU (solvers on
+ * several host threads or streams) race; the array keeps the last call's
+ * rows.  res_hist and the deferred status as ql_step.  Errors as ql_step,
+ * and QL_EINVAL (n_iter over the array's rows). */
+int ql_step_static(ql_solver *s, int32_t n_iter, double *res_hist);
+
 /* Residual norms of the last iteration ql_step ran (synchronises when that
  * call returned without a history).  Errors: QL_ESTATE, or the failure of
  * those iterations. */

@@ -163,6 +163,12 @@ hipError_t launch_resnorm(hipStream_t st, const double *R, int n, int nchunk, co
                           double *part, int ncase, const int *chunk_ptr, const double *inv_nupd,
                           int *ctr, int cap, double *hist, const Retire &rt,
                           const int *case_of, uint8_t *tile_active);
+// Fixed device array (kScratchDoubles doubles, per GPU) that holds the
+// residual history of ql_step_static; scratch_address returns its address
+// on the current device.
+constexpr int kScratchDoubles = 1 << 16;
+hipError_t scratch_address(double **ptr);
+
 hipError_t launch_forces(hipStream_t st, int nw, const int *wall, const double2 *xy,
                          const double2 *nrm, const double *U, int n, double gamma, double pinf,
                          double *scratch, double *out);

@@ -1919,4 +1919,13 @@ hipError_t launch_forces(hipStream_t st, int nw, const int *wall, const double2 
     return hipGetLastError();
 }
 
+// Residual history of ql_step_static, for callers that cannot allocate:
+// file-scope, so every GPU the library runs on holds one copy until the
+// process ends.  Host code uses only the address scratch_address returns.
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+hipError_t scratch_address(double **ptr) {
+    return hipGetSymbolAddress((void **)ptr, HIP_SYMBOL(scratch));
+}
+
 }  // namespace ql

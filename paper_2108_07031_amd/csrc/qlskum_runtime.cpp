@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -105,8 +106,13 @@ struct ql_solver {
     int *bt_iters = nullptr;
     bool retire_on = false;  // iterations enqueued now retire cases on the device
     // ql_step without a history: the iterations' status and last norms are
-    // collected by the next call (rows of history written)
+    // collected by the next call (rows of history written, and where)
     int step_pending = 0;
+    const double *pending_hist = nullptr;
+    // ql_step_static: this device's fixed history array, and the flag that
+    // keeps the iterations it enqueues free of allocating calls
+    double *scratch = nullptr;
+    bool no_alloc = false;
     int qcur = 0, gfin = 0;
     std::vector<double> last_res;  // [ncase][4]
     std::vector<int32_t> case_status;  // per case, of the last ql_batch_run
@@ -485,13 +491,13 @@ struct Timer {
     int kind;
     hipEvent_t a = nullptr;
     Timer(ql_solver *s_, int k) : s(s_), kind(k) {
-        if (s->timing && !s->capturing) {
+        if (s->timing && !s->capturing && !s->no_alloc) {
             a = take_event(s);
             if (a) (void)hipEventRecord(a, s->stream);
         }
     }
     void done() {
-        if (s->timing && !s->capturing && a) {
+        if (s->timing && !s->capturing && !s->no_alloc && a) {
             hipEvent_t b = take_event(s);
             if (b) (void)hipEventRecord(b, s->stream);
             s->pending.push_back({kind, a, b});
@@ -583,7 +589,8 @@ int launch_stage(ql_solver *s, const DevCloud &c, const FlowParams &fp, int stag
 
 // Enqueue one pseudo-time iteration: four stages, then the residual norms of
 // stage 1 into history row *ctr.
-int enqueue_iteration(ql_solver *s, const DevCloud &c, const FlowParams &fp, int hist_cap) {
+int enqueue_iteration(ql_solver *s, const DevCloud &c, const FlowParams &fp, int hist_cap,
+                      double *hist) {
     for (int rk = 1; rk <= 4; ++rk) {
         int st = QL_OK;
         // the first-order scheme needs no q-derivatives
@@ -599,7 +606,7 @@ int enqueue_iteration(ql_solver *s, const DevCloud &c, const FlowParams &fp, int
                     s->case_active, s->case_err};
     HIPCHK(s, launch_resnorm(s->stream, s->R, s->n, s->nchunk, s->chunk_beg, s->part, s->ncase,
                              s->chunk_ptr, s->inv_nupd + (fp.kobc ? s->ncase : 0), s->ctr,
-                             hist_cap, s->reshist, rt, s->case_of, s->tile_active));
+                             hist_cap, hist, rt, s->case_of, s->tile_active));
     t.done();
     return QL_OK;
 }
@@ -632,7 +639,7 @@ int capture_iteration(ql_solver *s) {
     const int q0 = s->qcur;
     HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
     s->capturing = true;
-    int st = enqueue_iteration(s, c, fp, s->reshist_cap / s->ncase);
+    int st = enqueue_iteration(s, c, fp, s->reshist_cap / s->ncase, s->reshist);
     s->capturing = false;
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(s->stream, &g);
@@ -656,6 +663,21 @@ void drop_graph(ql_solver *s) {
     s->graph_qcur = -1;
 }
 
+// Address of this library's fixed history array on `device` (looked up once
+// per device, with the device current; each GPU holds its own copy).
+hipError_t scratch_of_device(int device, double **ptr) {
+    static std::mutex mu;
+    static std::vector<double *> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)addr.size() <= device) addr.resize(device + 1, nullptr);
+    if (!addr[device]) {
+        const hipError_t e = scratch_address(&addr[device]);
+        if (e != hipSuccess) return e;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
+
 // Collect the outcome of iterations that ql_step enqueued without a
 // history: their last residual norms and the error word (one
 // synchronisation).  A failure is returned to the call that collects it.
@@ -664,13 +686,11 @@ int settle(ql_solver *s) {
     const size_t row = (size_t)s->step_pending - 1;
     s->step_pending = 0;
     (void)hipSetDevice(s->device);
-    std::vector<double> last((size_t)4 * s->ncase);
-    HIPCHK(s, hipMemcpyAsync(last.data(), s->reshist + row * s->ncase * 4,
-                             sizeof(double) * last.size(), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->last_res.data(), s->pending_hist + row * s->ncase * 4,
+                             sizeof(double) * 4 * s->ncase, hipMemcpyDeviceToHost, s->stream));
     const int st = sync_and_check(s, "step");
     harvest_timing(s);
     if (st) return st;
-    s->last_res = last;
     s->has_res = true;
     return QL_OK;
 }
@@ -720,6 +740,10 @@ int ql_create(ql_solver **out, int32_t device, void *hip_stream) {
         return QL_EDEVICE;
     }
     if (hipSetDevice(device) != hipSuccess) {
+        delete s;
+        return QL_EDEVICE;
+    }
+    if (scratch_of_device(device, &s->scratch) != hipSuccess) {
         delete s;
         return QL_EDEVICE;
     }
@@ -1110,10 +1134,11 @@ int ql_step(ql_solver *s, int32_t n_iter, double *res_hist) {
     if ((st = reset_err(s))) return st;
     if ((st = reset_counter(s))) return st;
     for (int it = 0; it < n_iter; ++it)
-        if ((st = enqueue_iteration(s, c, fp, s->reshist_cap / s->ncase))) return st;
+        if ((st = enqueue_iteration(s, c, fp, s->reshist_cap / s->ncase, s->reshist))) return st;
     s->has_eval = false;
     if (!res_hist) {  // no synchronisation: the next call collects the outcome
         s->step_pending = n_iter;
+        s->pending_hist = s->reshist;
         s->has_res = false;
         return QL_OK;
     }
@@ -1127,6 +1152,42 @@ int ql_step(ql_solver *s, int32_t n_iter, double *res_hist) {
     if (st) return st;
     if (res_hist) std::memcpy(res_hist, hist.data(), sizeof(double) * rows);
     std::memcpy(s->last_res.data(), &hist[rows - (size_t)4 * s->ncase],
+                sizeof(double) * 4 * s->ncase);
+    s->has_res = true;
+    return QL_OK;
+}
+
+int ql_step_static(ql_solver *s, int32_t n_iter, double *res_hist) {
+    int st = ensure_ready(s, true);
+    if (st) return st;
+    if (n_iter < 0) return fail(s, QL_EINVAL, "n_iter < 0");
+    if (n_iter == 0) return QL_OK;
+    const int cap = kScratchDoubles / (4 * s->ncase);
+    if (n_iter > cap)
+        return fail(s, QL_EINVAL, "ql_step_static: n_iter = %d exceeds %d rows of %d case(s)",
+                    n_iter, cap, s->ncase);
+    (void)hipSetDevice(s->device);
+    const DevCloud c = dev_cloud(s);
+    const FlowParams fp = flow_params(s);
+    if ((st = reset_err(s)) || (st = reset_counter(s))) return st;
+    // the same iterations as ql_step, with no timing events and the history
+    // rows in this device's fixed array
+    s->no_alloc = true;
+    for (int it = 0; it < n_iter && !st; ++it) st = enqueue_iteration(s, c, fp, cap, s->scratch);
+    s->no_alloc = false;
+    if (st) return st;
+    s->has_eval = false;
+    const size_t rows = (size_t)n_iter * s->ncase * 4;
+    if (!res_hist) {
+        s->step_pending = n_iter;
+        s->pending_hist = s->scratch;
+        s->has_res = false;
+        return QL_OK;
+    }
+    HIPCHK(s, hipMemcpyAsync(res_hist, s->scratch, sizeof(double) * rows, hipMemcpyDeviceToHost,
+                             s->stream));
+    if ((st = sync_and_check(s, "step_static"))) return st;
+    std::memcpy(s->last_res.data(), res_hist + rows - (size_t)4 * s->ncase,
                 sizeof(double) * 4 * s->ncase);
     s->has_res = true;
     return QL_OK;
@@ -1573,7 +1634,7 @@ int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_ever
                     st = fail(s, QL_EDEVICE, "graph launch failed");
             if (st) break;
         } else {
-            for (int it = 0; it < k && !st; ++it) st = enqueue_iteration(s, c, fp, block);
+            for (int it = 0; it < k && !st; ++it) st = enqueue_iteration(s, c, fp, block, s->reshist);
             if (st) break;
         }
         HIPCHK(s, hipMemcpyAsync(active.data(), s->case_active, nc, hipMemcpyDeviceToHost,

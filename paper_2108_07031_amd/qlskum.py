@@ -26,7 +26,8 @@ QL_SPLIT_S_PLUS, QL_SPLIT_S_MINUS, QL_SPLIT_N_PLUS, QL_SPLIT_N_MINUS = 1, 2, 4, 
 
 # every entry point the public header declares
 EXPORTS = ("ql_default_params", "ql_create", "ql_destroy", "ql_upload_cloud", "ql_set_params",
-           "ql_init_freestream", "ql_set_state", "ql_step", "ql_residual_norm",
+           "ql_init_freestream", "ql_set_state", "ql_step", "ql_step_static",
+           "ql_residual_norm",
            "ql_fetch_state", "ql_forces", "ql_last_error", "ql_evaluate", "ql_debug_fetch",
            "ql_debug_flags", "ql_cloud_size", "ql_set_timing", "ql_kernel_time",
            "ql_batch_upload", "ql_batch_info", "ql_batch_run", "ql_batch_status",
@@ -66,6 +67,7 @@ def _load():
     lib.ql_init_freestream.argtypes = [vp]
     lib.ql_set_state.argtypes = [vp, vp, i32, i32]
     lib.ql_step.argtypes = [vp, i32, vp]
+    lib.ql_step_static.argtypes = [vp, i32, vp]
     lib.ql_residual_norm.argtypes = [vp, vp]
     lib.ql_fetch_state.argtypes = [vp, vp, i32]
     lib.ql_forces.argtypes = [vp, P(d), P(d)]
@@ -191,6 +193,17 @@ def ql_step(s, n_iter, want_history=True):
     nc = ql_batch_info(s)
     hist = np.zeros((max(n_iter, 1), nc, 4)) if want_history else None
     _check(s, lib.ql_step(s, int(n_iter), hist.ctypes.data if want_history else None))
+    if not want_history:
+        return None
+    return hist[:n_iter, 0] if nc == 1 else hist[:n_iter]
+
+
+def ql_step_static(s, n_iter, want_history=True):
+    """ql_step with its residual history in the library's fixed device
+    array (no device allocation); same return value as ql_step."""
+    nc = ql_batch_info(s)
+    hist = np.zeros((max(int(n_iter), 1), nc, 4))
+    _check(s, lib.ql_step_static(s, int(n_iter), hist.ctypes.data if want_history else None))
     if not want_history:
         return None
     return hist[:n_iter, 0] if nc == 1 else hist[:n_iter]
@@ -548,6 +561,9 @@ class Solver:
 
     def step(self, n_iter, want_history=True):
         return ql_step(self.h, n_iter, want_history)
+
+    def step_static(self, n_iter, want_history=True):
+        return ql_step_static(self.h, n_iter, want_history)
 
     def residual_norm(self):
         return ql_residual_norm(self.h)
