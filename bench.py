@@ -311,6 +311,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--accuracy-iters", type=int, default=1000, metavar="N",
+                    help="continue both timed runs (untimed) to N iterations and compare "
+                         "mixed with FP64 lift, drag and density (0: skip)")
     ap.add_argument("--no-warm-study", action="store_true")
     ap.add_argument("--no-batch-study", action="store_true")
     ap.add_argument("--precision", choices=("both", "fp64", "mixed"), default="both")
@@ -374,9 +377,19 @@ def main():
             log(f"  {name}: {cnt} launches, avg {ms / max(cnt, 1) * 1e3:.1f} us, "
                 f"share {ms / gpu_ms * 100:.1f}%")
         cl, cd = s.forces()
+        acc = None
+        more = args.accuracy_iters - args.warmup - args.steps
+        if args.accuracy_iters > 0 and args.precision == "both":
+            # the same run continued (untimed) to a fixed iteration count, for
+            # the FP64 vs mixed comparison of lift, drag and density
+            if more > 0:
+                log(f"[{PREC_NAME[precision]}] continued to {args.accuracy_iters} iterations")
+                s.step(more, want_history=False)
+            acc = dict(iterations=max(args.accuracy_iters, args.warmup + args.steps),
+                       cl_cd=s.forces(), rho=s.fetch_state()[0].copy())
         s.close()
         elapsed = max(wall, gpu_ms / 1e3)
-        return dict(flags=flags, elapsed=elapsed, ktime=ktime, hist=hist, cl=cl, cd=cd,
+        return dict(flags=flags, elapsed=elapsed, ktime=ktime, hist=hist, cl=cl, cd=cd, acc=acc,
                     value=cloud.n * args.steps / elapsed / 1e6)
 
     if args.copy_calibration > 0:
@@ -435,6 +448,17 @@ def main():
                         "ms_per_step": runs[1]["elapsed"] * 1e3 / args.steps,
                         "over_fp64": runs[1]["value"] / runs[0]["value"],
                         "dtype": "f32 flux body, f64 sums and update"}
+        a0, a1 = runs[0]["acc"], runs[1]["acc"]
+        if a0 and a1:
+            # mixed vs FP64 from the same freestream start after the same
+            # number of iterations (the configuration's 1000)
+            out["mixed"]["vs_fp64"] = {
+                "iterations": a0["iterations"],
+                "cl_cd_fp64": list(a0["cl_cd"]), "cl_cd_mixed": list(a1["cl_cd"]),
+                "abs_dcl": abs(a1["cl_cd"][0] - a0["cl_cd"][0]),
+                "abs_dcd": abs(a1["cl_cd"][1] - a0["cl_cd"][1]),
+                "density_max_rel": float(np.abs(a1["rho"] - a0["rho"]).max()
+                                         / np.abs(a0["rho"]).max())}
     if not headline:
         args.no_batch_study = args.no_warm_study = args.no_cpu_baseline = True
     if not args.no_batch_study:

@@ -107,6 +107,12 @@ typedef struct {
                          count in the residual norm.  Needs non-singular
                          s+, s-, n+ stencils at every outer point
                          (QL_ESINGULAR otherwise, at upload or here)      */
+    int32_t pad0;     /* reserved, 0                                           */
+    double mixed_switch; /* precision 1 in ql_batch_run: a case whose density
+                         residual norm falls to mixed_switch x its reference
+                         continues with FP64 split fluxes (the FP32 flux body
+                         resolves the residual only to a few 1e-6 of its
+                         first value); 0 = never.  In [0, 1)                */
 } ql_params;
 
 /* Fill *p with the defaults: gamma 1.4, M 0.63, alpha 2, CFL 0.2, 3 inner
@@ -262,6 +268,11 @@ int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_ever
  * was retired), QL_EDIVERGED (its norm blew up).  status holds ncase entries (ql_batch_info); all QL_OK
  * before any run.  Errors: QL_EINVAL (NULL), QL_ESTATE (no cloud). */
 int ql_batch_status(const ql_solver *s, int32_t *status);
+
+/* Iteration of the last ql_batch_run after which case c moved from FP32 to
+ * FP64 split fluxes (params.mixed_switch), or -1: iter[ncase].
+ * Errors: QL_EINVAL (NULL), QL_ESTATE (no cloud). */
+int ql_batch_switched(const ql_solver *s, int32_t *iter);
 
 /* Lift and drag of every case (as ql_forces), cl[ncase], cd[ncase]. */
 int ql_batch_forces(ql_solver *s, double *cl, double *cd);

@@ -25,9 +25,11 @@ FMA_LIB = os.path.join(_HERE, "liboracle_fma.so")
 
 def build(cflags=("-O2", "-ffp-contract=off"), out=_LIB):
     """Compile the oracle with gcc (no FMA contraction) into a shared library."""
-    cmd = ["gcc", "-std=c99", *cflags, "-fPIC", "-shared", "-o", out + ".tmp", _SRC, "-lm"]
+    # a per-process temporary: parallel test workers may build at once
+    tmp = f"{out}.tmp{os.getpid()}"
+    cmd = ["gcc", "-std=c99", *cflags, "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(out + ".tmp", out)
+    os.replace(tmp, out)
     return out
 
 

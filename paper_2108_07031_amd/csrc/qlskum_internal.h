@@ -59,6 +59,10 @@ struct DevCloud {
     const uint8_t *tile_active;
     // batched runs: error word of each case [ncase] (nullable)
     ErrWord *case_err;
+    // split fluxes of tile t in FP32 (1) or FP64 (0) when a mixed-precision
+    // run moves cases to FP64 fluxes: the FP64 and the mixed flux kernels
+    // each take only their tiles (null: one kernel takes every tile)
+    const uint8_t *tile_prec;
     // conserved freestream of each case [ncase][4] (the kinetic outer
     // condition's far-field Maxwellian)
     const double *uinf;
@@ -98,6 +102,12 @@ struct Retire {
     double *last;
     uint8_t *active;
     const ErrWord *case_err;
+    // precision switch (nullable): a case with prec[c] = 1 (FP32 fluxes)
+    // whose norm is <= *sw * ref[c] gets prec[c] = 0 and sw_iter[c] = the
+    // iteration; the tiles holding it then run FP64 fluxes
+    const double *sw;
+    uint8_t *prec;
+    int *sw_iter;
 };
 
 int num_blocks(int n);
@@ -117,11 +127,11 @@ hipError_t launch_unpermute_state(hipStream_t st, int n, const double *U, const 
                                   double *Uuser);
 hipError_t launch_prep(hipStream_t st, const DevCloud &c, const FlowParams &fp, const double *U,
                        double *Un, double2 *q, double *dt, float4 *q32, ErrWord *err);
-// q-derivatives (tiled like the flux sweep; lds_budget as there): first
-// pass with the limiter bounds (qmm: qmax - q and qmin - q per point), and
-// one inner iteration from the first pass g0 and the previous iterate gprev.
-// gnext may be null when only the FP32 shadow (g32) is wanted, and qmm when
-// only the bounds' FP32 shadow (sh.qmm32) is.
+// q-derivatives (tiled like the flux sweep; lds_budget as there, 0 for the
+// default): first pass with the limiter bounds (qmm: qmax - q and qmin - q
+// per point), and one inner iteration from the first pass g0 and the
+// previous iterate gprev.  gnext may be null when only the FP32 shadow
+// (g32) is wanted, and qmm when only the bounds' FP32 shadow (sh.qmm32) is.
 hipError_t launch_grad0(hipStream_t st, const DevCloud &c, int lds_budget, const double2 *q,
                         double2 *g, double2 *qmm, int want_bounds, Shadow sh);
 hipError_t launch_gradk(hipStream_t st, const DevCloud &c, int lds_budget, const double2 *g0,
@@ -158,11 +168,12 @@ hipError_t launch_select_state(hipStream_t st, int n, const int *case_of, const 
 hipError_t launch_wall_distance(hipStream_t st, int n, const double2 *xy, const int *case_of,
                                 const int *wall_lo, const int *wall, double *d);
 // residual norms per case into history row *ctr (then *ctr += 1); with
-// rt.on, the retirement of cases and the tile activity that follows from it
+// rt.on, the retirement of cases and the tile activity (and, with rt.prec,
+// the tile precision) that follows from it
 hipError_t launch_resnorm(hipStream_t st, const double *R, int n, int nchunk, const int *chunk_beg,
                           double *part, int ncase, const int *chunk_ptr, const double *inv_nupd,
                           int *ctr, int cap, double *hist, const Retire &rt,
-                          const int *case_of, uint8_t *tile_active);
+                          const int *case_of, uint8_t *tile_active, uint8_t *tile_prec);
 // Fixed device array (kScratchDoubles doubles, per GPU) that holds the
 // residual history of ql_step_static; scratch_address returns its address
 // on the current device.

@@ -284,17 +284,24 @@ __global__ void __launch_bounds__(kBlock) k_warm_state(int n, const int *__restr
     if (kind[p] != kOuter) {
         const float *y = Y + 4 * (size_t)perm[p];
         double pr[4];
+        bool ok = true;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) pr[c] = (double)sc.mean[c] + (double)sc.std[c] * (double)y[c];
-        const double pinf = 1.0 / gamma;  // rho_inf = 1, c_inf = 1
-        const double rho = fmax(pr[0], sc.floor);
-        const double pp = fmax(pr[3], sc.floor * pinf);
-        v[0] = rho;
-        v[1] = rho * pr[1];
-        v[2] = rho * pr[2];
-        v[3] = pp / (gamma - 1.0) + 0.5 * rho * (pr[1] * pr[1] + pr[2] * pr[2]);
-        if (!(isfinite(v[1]) && isfinite(v[2]) && isfinite(v[3]))) {
-            v[0] = u[0]; v[1] = u[1]; v[2] = u[2]; v[3] = u[3];
+        for (int c = 0; c < 4; ++c) {
+            pr[c] = (double)sc.mean[c] + (double)sc.std[c] * (double)y[c];
+            ok = ok && isfinite(pr[c]);
+        }
+        // a point whose primitive or conserved state is not finite keeps the
+        // freestream (fmax would hide a NaN density or pressure)
+        if (ok) {
+            const double pinf = 1.0 / gamma;  // rho_inf = 1, c_inf = 1
+            const double rho = fmax(pr[0], sc.floor);
+            const double pp = fmax(pr[3], sc.floor * pinf);
+            const double w[4] = {rho, rho * pr[1], rho * pr[2],
+                                 pp / (gamma - 1.0) + 0.5 * rho * (pr[1] * pr[1] + pr[2] * pr[2])};
+            ok = isfinite(w[0]) && isfinite(w[1]) && isfinite(w[2]) && isfinite(w[3]);
+            if (ok) {
+                v[0] = w[0]; v[1] = w[1]; v[2] = w[2]; v[3] = w[3];
+            }
         }
         if (kind[p] == kWall) wall_project(v, nrm[p]);
     }
@@ -745,17 +752,27 @@ static int lds_cap(const DevCloud &c, int budget, int rec) {
     return min(c.fmax_slots, max(budget / rec, 0));
 }
 
+// LDS bytes a q-derivative workgroup stages its tile image in when the
+// caller gives no budget (records of 48 and 80 bytes; the inner iteration
+// also stages 4 KB of entry slots).  Sized so that the 6 workgroups per CU
+// that the kernels' registers allow stay resident in 160 KB of LDS
+// (measured on the 2.5M cloud: 22 KB runs the inner iteration 12% faster
+// than 36 KB, although a few more tiles then read from memory).
+constexpr int kGrad0Lds = 32 * 1024;
+constexpr int kGradkLds = 22 * 1024;
+
 hipError_t launch_grad0(hipStream_t st, const DevCloud &c, int lds_budget, const double2 *q,
                         double2 *g, double2 *qmm, int want_bounds, Shadow sh) {
     const int rec = 3 * (int)sizeof(double2);
-    const int cap = lds_cap(c, lds_budget, rec);
+    const int cap = lds_cap(c, lds_budget > 0 ? lds_budget : kGrad0Lds, rec);
+    const int ntile = num_flux_tiles(c.n);
     if (want_bounds && !qmm) {
         if (!sh.qmm32) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_grad0<false>, dim3(num_flux_tiles(c.n)), dim3(kBlock),
-                           (size_t)cap * rec, st, c, cap, q, g, qmm, want_bounds, sh);
+        hipLaunchKernelGGL(k_grad0<false>, dim3(ntile), dim3(kBlock), (size_t)cap * rec, st, c, cap,
+                           q, g, qmm, want_bounds, sh);
     } else {
-        hipLaunchKernelGGL(k_grad0<true>, dim3(num_flux_tiles(c.n)), dim3(kBlock),
-                           (size_t)cap * rec, st, c, cap, q, g, qmm, want_bounds, sh);
+        hipLaunchKernelGGL(k_grad0<true>, dim3(ntile), dim3(kBlock), (size_t)cap * rec, st, c, cap,
+                           q, g, qmm, want_bounds, sh);
     }
     return hipGetLastError();
 }
@@ -764,10 +781,11 @@ hipError_t launch_gradk(hipStream_t st, const DevCloud &c, int lds_budget, const
                         const double2 *gprev, double2 *gnext, float4 *g32) {
     const int rec = 5 * (int)sizeof(double2);
     // the image and the entry slots share the workgroup's 160 KB of LDS
-    const int cap = min(lds_cap(c, lds_budget, rec), (kLdsBytes - 2 * kCapE) / rec);
+    const int cap = min(lds_cap(c, lds_budget > 0 ? lds_budget : kGradkLds, rec),
+                        (kLdsBytes - 2 * kCapE) / rec);
     const size_t shmem = cap > 0 ? (size_t)cap * rec + 2 * kCapE : 0;
-    hipLaunchKernelGGL(k_gradk, dim3(num_flux_tiles(c.n)), dim3(kBlock), shmem, st, c,
-                       cap, g0, gprev, gnext, g32);
+    hipLaunchKernelGGL(k_gradk, dim3(num_flux_tiles(c.n)), dim3(kBlock), shmem, st, c, cap, g0,
+                       gprev, gnext, g32);
     return hipGetLastError();
 }
 
@@ -1222,6 +1240,7 @@ k_flux(DevCloud cl, FlowParams fp, int stage, int cap,
     const int n = cl.n;
     const int t = logical_block();
     if (cl.tile_active && !cl.tile_active[t]) return;
+    if (cl.tile_prec && cl.tile_prec[t] != 0) return;  // an FP32-flux tile
     const int base = t * kFluxTile;
     const int nown = min(kFluxTile, n - base);
     int h0 = 0, ns = 0;
@@ -1665,6 +1684,7 @@ k_flux_mixed(
     const int n = cl.n;
     const int t = logical_block();
     if (cl.tile_active && !cl.tile_active[t]) return;
+    if (cl.tile_prec && cl.tile_prec[t] != 1) return;  // an FP64-flux tile
     const int base = t * kFluxTile;
     const int nown = min(kFluxTile, n - base);
     int h0 = 0, ns = 0;
@@ -1833,6 +1853,10 @@ __global__ void __launch_bounds__(kBlock) k_res_cases(int ncase, const int *__re
             for (int c = 0; c < 4; ++c) rt.last[4 * cs + c] = nv[c];
             double ref = rt.ref[cs];
             if (ref < 0.0) ref = rt.ref[cs] = nv[0];
+            if (rt.prec && rt.prec[cs] && nv[0] <= *rt.sw * ref) {
+                rt.prec[cs] = 0;
+                rt.sw_iter[cs] = rt.iters[cs];
+            }
             if (rt.case_err[cs] != kErrClear || nv[0] <= drop * ref ||
                 nv[0] > kDiverged * ref || !(nv[0] == nv[0]))
                 rt.active[cs] = 0;
@@ -1841,30 +1865,38 @@ __global__ void __launch_bounds__(kBlock) k_res_cases(int ncase, const int *__re
     if (threadIdx.x == 0) *ctr = row + 1;
 }
 
-// tile t is skipped by every tiled sweep when no case it holds is active
+// tile t is skipped by every tiled sweep when no case it holds is active;
+// its split fluxes are FP32 only while every case it holds is (case_prec
+// nullable: no precision switch)
 __global__ void __launch_bounds__(kBlock) k_tile_active(int n, int ntile,
                                                         const int *__restrict__ case_of,
                                                         const uint8_t *__restrict__ case_active,
-                                                        uint8_t *__restrict__ tile_active) {
+                                                        uint8_t *__restrict__ tile_active,
+                                                        const uint8_t *__restrict__ case_prec,
+                                                        uint8_t *__restrict__ tile_prec) {
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= ntile) return;
     const int b = t * kFluxTile, e = min(n, b + kFluxTile) - 1;
-    uint8_t any = 0;
-    for (int c = case_of[b]; c <= case_of[e]; ++c) any |= case_active[c];
+    uint8_t any = 0, all32 = 1;
+    for (int c = case_of[b]; c <= case_of[e]; ++c) {
+        any |= case_active[c];
+        if (case_prec) all32 &= case_prec[c];
+    }
     tile_active[t] = any;
+    if (case_prec) tile_prec[t] = all32;
 }
 
 hipError_t launch_resnorm(hipStream_t st, const double *R, int n, int nchunk, const int *chunk_beg,
                           double *part, int ncase, const int *chunk_ptr, const double *inv_nupd,
                           int *ctr, int cap, double *hist, const Retire &rt,
-                          const int *case_of, uint8_t *tile_active) {
+                          const int *case_of, uint8_t *tile_active, uint8_t *tile_prec) {
     hipLaunchKernelGGL(k_res_chunks, dim3(nchunk), dim3(kBlock), 0, st, R, n, chunk_beg, part);
     hipLaunchKernelGGL(k_res_cases, dim3(1), dim3(kBlock), 0, st, ncase, chunk_ptr, part,
                        inv_nupd, ctr, cap, hist, rt);
     if (rt.on) {
         const int ntile = num_flux_tiles(n);
         hipLaunchKernelGGL(k_tile_active, dim3((ntile + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
-                           n, ntile, case_of, rt.active, tile_active);
+                           n, ntile, case_of, rt.active, tile_active, rt.prec, tile_prec);
     }
     return hipGetLastError();
 }

@@ -105,6 +105,13 @@ struct ql_solver {
     double *bt_ref = nullptr, *bt_last = nullptr, *bt_drop = nullptr;
     int *bt_iters = nullptr;
     bool retire_on = false;  // iterations enqueued now retire cases on the device
+    // precision switch of mixed batched runs: per-case and per-tile flux
+    // precision (1 FP32, 0 FP64), the switch threshold and iteration
+    uint8_t *case_prec = nullptr, *tile_prec = nullptr;
+    double *bt_switch = nullptr;
+    int *bt_swit = nullptr;
+    bool hybrid = false;  // iterations enqueued now run both flux kernels
+    std::vector<int32_t> case_switch;  // per case, of the last ql_batch_run
     // ql_step without a history: the iterations' status and last norms are
     // collected by the next call (rows of history written, and where)
     int step_pending = 0;
@@ -121,6 +128,7 @@ struct ql_solver {
     // one pseudo-time iteration captured as a graph (batched runs)
     hipGraphExec_t graph = nullptr;
     int graph_qcur = -1;
+    bool graph_hybrid = false;  // the captured iteration runs both flux kernels
     bool capturing = false;
 
     bool timing = false;
@@ -177,7 +185,9 @@ void free_cloud(ql_solver *s) {
     dfree(s->dwall_lo); dfree(s->wctr); dfree(s->wsel); dfree(s->wres);
     dfree(s->case_active); dfree(s->tile_active); dfree(s->uinf); dfree(s->part);
     dfree(s->inv_nupd); dfree(s->case_err); dfree(s->bt_ref); dfree(s->bt_last);
-    dfree(s->bt_drop); dfree(s->bt_iters);
+    dfree(s->bt_drop); dfree(s->bt_iters); dfree(s->case_prec); dfree(s->tile_prec);
+    dfree(s->bt_switch); dfree(s->bt_swit);
+    s->case_switch.clear();
     s->step_pending = 0;
     if (s->graph) (void)hipGraphExecDestroy(s->graph);
     s->graph = nullptr;
@@ -371,6 +381,7 @@ DevCloud dev_cloud(const ql_solver *s) {
     c.tile_active = s->tile_active;
     c.uinf = s->uinf;
     c.case_err = s->case_err;
+    c.tile_prec = s->hybrid ? s->tile_prec : nullptr;
     return c;
 }
 
@@ -410,6 +421,8 @@ int check_params(ql_solver *s, const ql_params *p) {
     if (p->flux_split < 0 || p->flux_split > 2)
         return fail(s, QL_EINVAL, "flux_split must be 0, 1 or 2");
     if (p->outer_bc != 0 && p->outer_bc != 1) return fail(s, QL_EINVAL, "outer_bc must be 0 or 1");
+    if (!(p->mixed_switch >= 0.0 && p->mixed_switch < 1.0))
+        return fail(s, QL_EINVAL, "mixed_switch must lie in [0, 1)");
     if (p->outer_bc == 1 && s->has_cloud && s->outer_bad >= 0)
         return fail(s, QL_ESINGULAR,
                     "kinetic outer condition: singular split stencil at outer point %d",
@@ -505,15 +518,6 @@ struct Timer {
     }
 };
 
-// LDS bytes a q-derivative workgroup stages its tile image in (records of
-// 48 and 80 bytes; the inner iteration also stages 4 KB of entry slots).
-// Sized so that the 6 workgroups per CU that the kernels' registers allow
-// stay resident in 160 KB of LDS (measured on the 2.5M cloud: 22 KB runs
-// the inner iteration 12% faster than 36 KB, although a few more tiles then
-// read from memory).
-constexpr int kGrad0Lds = 32 * 1024;
-constexpr int kGradkLds = 22 * 1024;
-
 // One stage's q-derivatives: first pass + n_inner Jacobi iterations; leaves
 // the final iterate in g[gfin].  In mixed precision the flux reads only the
 // FP32 shadows, so unless fp64_out is set (inspection) neither the last
@@ -525,7 +529,8 @@ int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds, bool fp64_o
     // mixed precision: the last pass also writes the FP32 shadow of g, the
     // first pass the FP32 shadow of the bounds
     const bool mixed = s->prm.precision == 1;
-    const bool skip64 = mixed && !fp64_out;
+    // a run that switches cases to FP64 fluxes needs both forms
+    const bool skip64 = mixed && !fp64_out && !s->hybrid;
     Shadow sh{nullptr, nullptr, nullptr};
     if (mixed) {
         sh.qmm32 = s->qmm32;
@@ -533,7 +538,7 @@ int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds, bool fp64_o
     }
     {
         Timer t(s, 0);
-        HIPCHK(s, launch_grad0(s->stream, c, s->prm.grad_lds > 0 ? s->prm.grad_lds : kGrad0Lds,
+        HIPCHK(s, launch_grad0(s->stream, c, s->prm.grad_lds,
                                s->q[s->qcur], s->g[first], skip64 ? nullptr : s->qmm,
                                want_bounds ? 1 : 0, sh));
         t.done();
@@ -544,7 +549,7 @@ int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds, bool fp64_o
         const bool last = k == s->prm.n_inner - 1;
         float4 *g32 = (mixed && last) ? s->g32 : nullptr;
         Timer t(s, 1);
-        HIPCHK(s, launch_gradk(s->stream, c, s->prm.grad_lds > 0 ? s->prm.grad_lds : kGradkLds,
+        HIPCHK(s, launch_gradk(s->stream, c, s->prm.grad_lds,
                                s->g[2], s->g[cur], (skip64 && last) ? nullptr : s->g[nxt], g32));
         t.done();
         cur = nxt;
@@ -576,6 +581,20 @@ int flux_lds_budget(const ql_solver *s) {
 int launch_stage(ql_solver *s, const DevCloud &c, const FlowParams &fp, int stage, double *Rout) {
     const int a = s->qcur, b = 1 - s->qcur;
     const int lds = flux_lds_budget(s);
+    if (s->hybrid) {
+        // each kernel takes the tiles of its precision (tile_prec); the FP64
+        // one with its own default LDS budget
+        ql_params saved = s->prm;
+        s->prm.precision = 0;
+        const int lds64 = flux_lds_budget(s);
+        s->prm = saved;
+        HIPCHK(s, launch_flux(s->stream, c, fp, stage, lds64, s->q[a], s->g[s->gfin], s->qmm, s->U,
+                              s->Un, s->dt, s->q[b], Rout, s->q32[b], s->errw, 0, s->Rpart));
+        HIPCHK(s, launch_flux_mixed(s->stream, c, fp, stage, lds, s->q[a], s->q32[a], s->g32,
+                                    s->qmm32, s->U, s->Un, s->dt, s->q[b], s->q32[b], Rout,
+                                    s->errw));
+        return QL_OK;
+    }
     if (s->prm.precision == 1)
         HIPCHK(s, launch_flux_mixed(s->stream, c, fp, stage, lds, s->q[a], s->q32[a], s->g32,
                                     s->qmm32, s->U, s->Un, s->dt, s->q[b], s->q32[b], Rout,
@@ -603,10 +622,11 @@ int enqueue_iteration(ql_solver *s, const DevCloud &c, const FlowParams &fp, int
     }
     Timer t(s, 3);
     const Retire rt{s->retire_on ? 1 : 0, s->bt_drop, s->bt_ref, s->bt_iters, s->bt_last,
-                    s->case_active, s->case_err};
+                    s->case_active, s->case_err, s->bt_switch,
+                    s->hybrid ? s->case_prec : nullptr, s->bt_swit};
     HIPCHK(s, launch_resnorm(s->stream, s->R, s->n, s->nchunk, s->chunk_beg, s->part, s->ncase,
                              s->chunk_ptr, s->inv_nupd + (fp.kobc ? s->ncase : 0), s->ctr,
-                             hist_cap, hist, rt, s->case_of, s->tile_active));
+                             hist_cap, hist, rt, s->case_of, s->tile_active, s->tile_prec));
     t.done();
     return QL_OK;
 }
@@ -631,7 +651,7 @@ int reset_counter(ql_solver *s) {
 // Capture one iteration into s->graph (rows of history: capacity per replay
 // block is reshist_cap / ncase).
 int capture_iteration(ql_solver *s) {
-    if (s->graph && s->graph_qcur == s->qcur) return QL_OK;
+    if (s->graph && s->graph_qcur == s->qcur && s->graph_hybrid == s->hybrid) return QL_OK;
     if (s->graph) (void)hipGraphExecDestroy(s->graph);
     s->graph = nullptr;
     const DevCloud c = dev_cloud(s);
@@ -654,6 +674,7 @@ int capture_iteration(ql_solver *s) {
         return fail(s, QL_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e2));
     s->qcur = q0;  // capture enqueued nothing; the four stage flips cancel anyway
     s->graph_qcur = q0;
+    s->graph_hybrid = s->hybrid;
     return QL_OK;
 }
 
@@ -724,6 +745,8 @@ void ql_default_params(ql_params *p) {
     p->order = 2;
     p->flux_split = 0;
     p->outer_bc = 0;
+    p->pad0 = 0;
+    p->mixed_switch = 0.0;
 }
 
 int ql_create(ql_solver **out, int32_t device, void *hip_stream) {
@@ -936,6 +959,8 @@ static int upload_impl(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int
     HIPCHK(s, dalloc(&s->errw_outer, 1)); HIPCHK(s, dalloc(&s->case_err, ncase));
     HIPCHK(s, dalloc(&s->bt_ref, ncase)); HIPCHK(s, dalloc(&s->bt_last, (size_t)4 * ncase));
     HIPCHK(s, dalloc(&s->bt_drop, 1)); HIPCHK(s, dalloc(&s->bt_iters, ncase));
+    HIPCHK(s, dalloc(&s->case_prec, ncase)); HIPCHK(s, dalloc(&s->tile_prec, ntile));
+    HIPCHK(s, dalloc(&s->bt_switch, 1)); HIPCHK(s, dalloc(&s->bt_swit, ncase));
     s->case_err_clear.assign(ncase, kErrClear);
     HIPCHK(s, dalloc(&s->case_of, n)); HIPCHK(s, dalloc(&s->uinf, (size_t)4 * ncase));
     HIPCHK(s, dalloc(&s->case_active, ncase)); HIPCHK(s, dalloc(&s->tile_active, ntile));
@@ -1328,10 +1353,11 @@ static int warm_eval(ql_solver *s, const DevCloud &c, const FlowParams &fp) {
     if (st) return st;
     if ((st = run_gradients(s, c, fp.limiter != 0, false))) return st;
     if ((st = launch_stage(s, c, fp, 0, s->R))) return st;
-    const Retire off{0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    const Retire off{0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                     nullptr, nullptr, nullptr};
     HIPCHK(s, launch_resnorm(s->stream, s->R, s->n, s->nchunk, s->chunk_beg, s->part, s->ncase,
                              s->chunk_ptr, s->inv_nupd + (fp.kobc ? s->ncase : 0), s->wctr, 2,
-                             s->wres, off, s->case_of, s->tile_active));
+                             s->wres, off, s->case_of, s->tile_active, s->tile_prec));
     return QL_OK;
 }
 
@@ -1616,6 +1642,23 @@ int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_ever
                              s->stream));
     HIPCHK(s, hipMemcpyAsync(s->bt_drop, &drop_h, sizeof(double), hipMemcpyHostToDevice,
                              s->stream));
+    // mixed precision with a switch: every case starts with FP32 fluxes
+    const bool hybrid = s->prm.precision == 1 && s->prm.mixed_switch > 0.0 && s->prm.order == 2;
+    std::vector<int> swit(nc, -1);
+    const double sw_h = s->prm.mixed_switch;
+    if (hybrid) {
+        const std::vector<uint8_t> ones_c(nc, 1), ones_t(ntile, 1);
+        HIPCHK(s, hipMemcpyAsync(s->case_prec, ones_c.data(), nc, hipMemcpyHostToDevice,
+                                 s->stream));
+        HIPCHK(s, hipMemcpyAsync(s->tile_prec, ones_t.data(), ntile, hipMemcpyHostToDevice,
+                                 s->stream));
+        HIPCHK(s, hipMemcpyAsync(s->bt_swit, swit.data(), sizeof(int) * nc, hipMemcpyHostToDevice,
+                                 s->stream));
+        HIPCHK(s, hipMemcpyAsync(s->bt_switch, &sw_h, sizeof(double), hipMemcpyHostToDevice,
+                                 s->stream));
+        HIPCHK(s, hipStreamSynchronize(s->stream));  // the host vectors go out of scope
+    }
+    s->hybrid = hybrid;
     if ((st = reset_err(s)) || (st = reset_case_err(s))) return st;
     const DevCloud c = dev_cloud(s);
     const FlowParams fp = flow_params(s);
@@ -1645,7 +1688,11 @@ int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_ever
         done += k;
     }
     s->retire_on = false;
+    s->hybrid = false;
     if (st) return st;
+    if (hybrid)
+        HIPCHK(s, hipMemcpyAsync(swit.data(), s->bt_swit, sizeof(int) * nc, hipMemcpyDeviceToHost,
+                                 s->stream));
     HIPCHK(s, hipMemcpyAsync(iters.data(), s->bt_iters, sizeof(int) * nc, hipMemcpyDeviceToHost,
                              s->stream));
     HIPCHK(s, hipMemcpyAsync(last.data(), s->bt_last, sizeof(double) * 4 * nc,
@@ -1680,10 +1727,19 @@ int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_ever
     if ((st = reset_err(s)) || (st = reset_case_err(s))) return st;
     s->has_eval = false;
     s->case_status = status;
+    s->case_switch.assign(swit.begin(), swit.end());
     s->last_res = last;
     s->has_res = done > 0;
     if (iters_out) std::copy(iters.begin(), iters.end(), iters_out);
     if (res_out) std::copy(last.begin(), last.end(), res_out);
+    return QL_OK;
+}
+
+int ql_batch_switched(const ql_solver *s, int32_t *iter) {
+    if (!s || !iter) return QL_EINVAL;
+    if (!s->has_cloud) return QL_ESTATE;
+    for (int c = 0; c < s->ncase; ++c)
+        iter[c] = (c < (int)s->case_switch.size()) ? s->case_switch[c] : -1;
     return QL_OK;
 }
 

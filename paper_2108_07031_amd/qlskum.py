@@ -31,6 +31,7 @@ EXPORTS = ("ql_default_params", "ql_create", "ql_destroy", "ql_upload_cloud", "q
            "ql_fetch_state", "ql_forces", "ql_last_error", "ql_evaluate", "ql_debug_fetch",
            "ql_debug_flags", "ql_cloud_size", "ql_set_timing", "ql_kernel_time",
            "ql_batch_upload", "ql_batch_info", "ql_batch_run", "ql_batch_status",
+           "ql_batch_switched",
            "ql_batch_forces",
            "ql_flux_tiles", "ql_mlp_create", "ql_mlp_destroy", "ql_mlp_last_error",
            "ql_mlp_num_params", "ql_mlp_set_weights", "ql_mlp_get_weights", "ql_mlp_forward",
@@ -43,7 +44,8 @@ class ql_params(C.Structure):
                 ("cfl", C.c_double), ("n_inner", C.c_int32), ("limiter", C.c_int32),
                 ("venkat_k", C.c_double), ("precision", C.c_int32), ("reorder", C.c_int32),
                 ("flux_lds", C.c_int32), ("grad_lds", C.c_int32), ("order", C.c_int32),
-                ("flux_split", C.c_int32), ("outer_bc", C.c_int32)]
+                ("flux_split", C.c_int32), ("outer_bc", C.c_int32), ("pad0", C.c_int32),
+                ("mixed_switch", C.c_double)]
 
 
 class QLError(RuntimeError):
@@ -99,6 +101,7 @@ def _load():
     lib.ql_warm_start.argtypes = [vp, vp, vp, vp, d, vp, vp, vp]
     lib.ql_autotune.argtypes = [vp, C.c_char_p, vp]
     lib.ql_batch_status.argtypes = [vp, vp]
+    lib.ql_batch_switched.argtypes = [vp, vp]
     for name in EXPORTS:
         if name not in ("ql_default_params", "ql_last_error", "ql_mlp_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -243,6 +246,14 @@ def ql_batch_status(s):
     of a case that was retired)."""
     out = np.zeros(ql_batch_info(s), np.int32)
     _check(s, lib.ql_batch_status(s, out.ctypes.data))
+    return out
+
+
+def ql_batch_switched(s):
+    """Per case, the iteration of the last ql_batch_run after which it moved
+    from FP32 to FP64 split fluxes (-1: never)."""
+    out = np.zeros(ql_batch_info(s), np.int32)
+    _check(s, lib.ql_batch_switched(s, out.ctypes.data))
     return out
 
 
@@ -525,6 +536,9 @@ class Solver:
 
     def batch_status(self):
         return ql_batch_status(self.h)
+
+    def batch_switched(self):
+        return ql_batch_switched(self.h)
 
     def wall_distance(self):
         return ql_wall_distance(self.h)

@@ -73,23 +73,71 @@ def test_mixed_converged_forces(ql):
     60,000 iterations (measured: 45,696); the mixed path levels off near
     5.5e-6 of it -- the rounding floor of its FP32 flux body -- and must get
     below 1e-5; their lift and drag then agree within 1e-4 and the density
-    within 1e-3."""
+    within 1e-3.  With the precision switch (mixed_switch 3e-5: FP32 fluxes
+    until the residual is 3e-5 of its first value, FP64 fluxes after) the
+    mixed run reaches the six-decade drop, and its lift and drag agree with
+    the FP64 solution within 1e-4 (the accuracy target of the mixed path;
+    both runs converge to the same discrete solution, so the differences
+    printed are far smaller) and its density within 1e-4."""
     _say("mixed converged forces")
     c = cloud("c1")
     out = {}
-    for prec in (0, 1):
-        s = ql.Solver(c, precision=prec)
+    for name, prm in (("fp64", dict(precision=0)), ("mixed", dict(precision=1)),
+                      ("switch", dict(precision=1, mixed_switch=3e-5))):
+        s = ql.Solver(c, **prm)
         s.init_freestream()
         h = s.step(1)
         iters, res = s.batch_run(1e-6, 60000, check_every=1000, ref=h[:1, 0])
         drop = res[0, 0] / h[0, 0]
-        out[prec] = (s.forces(), s.fetch_state(), int(iters[0]), drop)
-        _say(f"  precision {prec}: {int(iters[0])} iterations, density residual drop {drop:.2e}, "
-             f"cl, cd {out[prec][0]}")
+        sw = int(s.batch_switched()[0])
+        out[name] = (s.forces(), s.fetch_state(), int(iters[0]), drop, sw)
+        _say(f"  {name}: {int(iters[0])} iterations, density residual drop {drop:.2e}, "
+             f"switched after {sw}, cl, cd {out[name][0]}")
         s.close()
-    (cl0, cd0), U0, it0, drop0 = out[0]
-    (cl1, cd1), U1, it1, drop1 = out[1]
+    (cl0, cd0), U0, it0, drop0, _ = out["fp64"]
+    (cl1, cd1), U1, it1, drop1, _ = out["mixed"]
+    (cl2, cd2), U2, it2, drop2, sw2 = out["switch"]
     assert it0 < 60000 and drop0 <= 1e-6, (it0, drop0)
     assert drop1 <= 1e-5, drop1
     assert abs(cl1 - cl0) <= 1e-4 and abs(cd1 - cd0) <= 1e-4
     assert normwise_rel(U1[:1], U0[:1]).max() <= 1e-3
+    assert it2 < 60000 and drop2 <= 1e-6, (it2, drop2)
+    assert 0 < sw2 < it2, (sw2, it2)
+    _say(f"  switch vs fp64: dcl {cl2 - cl0:.2e}, dcd {cd2 - cd0:.2e}, "
+         f"density {normwise_rel(U2[:1], U0[:1]).max():.2e}, FP32-flux share {sw2 / it2:.3f}")
+    assert abs(cl2 - cl0) <= 1e-4 and abs(cd2 - cd0) <= 1e-4
+    assert normwise_rel(U2[:1], U0[:1]).max() <= 1e-4
+
+
+def test_batched_switch_runs_every_case_to_the_drop(ql):
+    """Three clouds of different sizes and flow conditions in one mixed
+    batch with the precision switch: each case moves to FP64 fluxes on its
+    own (at a different iteration), reaches the six-decade drop, and its
+    lift and drag lie within 1e-4 of those of its solo FP64 run converged to
+    the same drop."""
+    from cloudgen import naca_ocloud
+    _say("batched precision switch")
+    cases = [dict(ns=48, nr=16, tau=0.12, mach=0.63, alpha=2.0),
+             dict(ns=64, nr=24, tau=0.10, mach=0.5, alpha=-1.5),
+             dict(ns=64, nr=24, tau=0.12, mach=0.6, alpha=1.0)]
+    clouds = [naca_ocloud(k["ns"], k["nr"], tau=k["tau"]) for k in cases]
+    s = ql.Solver(precision=1, mixed_switch=3e-5)
+    s.upload_batch(clouds, [k["mach"] for k in cases], [k["alpha"] for k in cases])
+    s.init_freestream()
+    iters, res = s.batch_run(1e-6, 100000, check_every=2000)
+    sw = s.batch_switched()
+    clb, cdb = s.batch_forces()
+    status = s.batch_status()
+    s.close()
+    _say(f"  iterations {list(iters)}, switched after {list(sw)}, status {list(status)}")
+    assert list(status) == [ql.QL_OK] * 3
+    for i, (cl, k) in enumerate(zip(clouds, cases)):
+        assert iters[i] < 100000 and 0 < sw[i] < iters[i]
+        so = ql.Solver(cl, mach=k["mach"], alpha_deg=k["alpha"])
+        so.init_freestream()
+        it, _ = so.batch_run(1e-6, 100000, check_every=2000)
+        cl0, cd0 = so.forces()
+        so.close()
+        _say(f"  case {i}: fp64 {int(it[0])} iterations; dcl {clb[i] - cl0:.2e}, "
+             f"dcd {cdb[i] - cd0:.2e}")
+        assert abs(clb[i] - cl0) <= 1e-4 and abs(cdb[i] - cd0) <= 1e-4

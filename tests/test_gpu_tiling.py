@@ -64,6 +64,42 @@ def test_flux_lds_budget_invariance(ql, precision, limiter):
         np.testing.assert_array_equal(U, out[0][2], err_msg=f"budget {b}")
 
 
+@pytest.mark.parametrize("case", ["hilbert", "caller", "dense"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_gradient_sweep_paths_bitwise(ql, case, precision):
+    """The q-derivative sweeps with their default LDS budgets (grad_lds 0)
+    against the same sweeps reading every record from memory (16) and with
+    a 24 KB budget: q-derivatives, bounds, residual and 10 iterations bit
+    for bit.  The clouds exercise each path: Hilbert order (the images in
+    LDS), the caller's order (most images over the budget: gathered from
+    memory), and a cloud with 36 neighbours per point (images in LDS, the
+    inner iteration's entry slot numbers over their 2048-entry buffer: read
+    from memory)."""
+    from cloudgen import random_cloud
+    _say(f"gradient sweep paths {case} precision={precision}")
+    if case == "dense":
+        c, reorder = random_cloud(3000, seed=5, k=36), 1
+        flow = dict(mach=0.5, alpha_deg=1.0)
+    else:
+        c, reorder = cloud("jitter"), (1 if case == "hilbert" else 0)
+        flow = dict(mach=0.85, alpha_deg=1.0)
+    U0 = smooth_state(c, **flow)
+    out = []
+    for b in (0, 16, 24 * 1024):
+        s = ql.Solver(c, precision=precision, limiter=1, reorder=reorder, grad_lds=b, **flow)
+        s.set_state(U0)
+        ev = s.evaluate()
+        s.set_state(U0)
+        h = s.step(10)
+        out.append((ev, h, s.fetch_state()))
+        s.close()
+    for b, (ev, h, U) in zip((16, 24 * 1024), out[1:]):
+        for key in ("g", "qmax", "qmin", "R"):
+            np.testing.assert_array_equal(ev[key], out[0][0][key], err_msg=f"{key} budget {b}")
+        np.testing.assert_array_equal(h, out[0][1], err_msg=f"history budget {b}")
+        np.testing.assert_array_equal(U, out[0][2], err_msg=f"state budget {b}")
+
+
 def test_flux_lds_budget_rejected(ql):
     _say("lds budget out of range")
     s = ql.Solver()
