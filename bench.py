@@ -311,6 +311,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--flux-split", type=int, default=0, choices=(0, 1, 2),
+                    help="FP64 flux sweep as one launch (0), s and n launches (1) or one "
+                         "launch per split stencil (2): the kernel-splitting ablation")
     ap.add_argument("--accuracy-iters", type=int, default=1000, metavar="N",
                     help="continue both timed runs (untimed) to N iterations and compare "
                          "mixed with FP64 lift, drag and density (0: skip)")
@@ -351,7 +354,8 @@ def main():
 
     def timed_run(precision):
         t_up = time.perf_counter()
-        s = ql.Solver(cloud, stream=stream, precision=precision, reorder=reorder, **FLOW)
+        split = dict(flux_split=args.flux_split) if precision == 0 else {}
+        s = ql.Solver(cloud, stream=stream, precision=precision, reorder=reorder, **split, **FLOW)
         log(f"[{PREC_NAME[precision]}] upload {time.perf_counter() - t_up:.1f} s")
         flags = s.flags()
         s.init_freestream()

@@ -381,7 +381,9 @@ int ql_autotune(ql_solver *s, const char *cache_path, int32_t *chosen);
  * After ql_evaluate all six hold that evaluation; after ql_step, 0 and 3
  * hold the current state's q and time step.  The bounds are kept as offsets
  * from q (what the limiter uses) and returned as q plus that offset, within
- * an ulp of the bound.  Errors: QL_EINVAL, QL_ESTATE. */
+ * an ulp of the bound.  In mixed precision (precision 1, no precision
+ * switch) q, g and the bounds are the FP32 values the flux sweep reads,
+ * widened.  Errors: QL_EINVAL, QL_ESTATE. */
 int ql_debug_fetch(ql_solver *s, int32_t what, double *out);
 
 /* Copy the split-membership flags to uint8 out[nnz] in the caller's CSR

@@ -136,6 +136,14 @@ hipError_t launch_grad0(hipStream_t st, const DevCloud &c, int lds_budget, const
                         double2 *g, double2 *qmm, int want_bounds, Shadow sh);
 hipError_t launch_gradk(hipStream_t st, const DevCloud &c, int lds_budget, const double2 *g0,
                         const double2 *gprev, double2 *gnext, float4 *g32);
+// mixed precision: the same sweeps gathering FP32 data (q32 for the first
+// pass, the previous FP32 iterate for an inner iteration) with FP64
+// positions, differences, sums and solves; FP32 results ([n][2] float4:
+// q_x[0..3], q_y[0..3]; bound offsets qmax - q, qmin - q)
+hipError_t launch_grad0_f(hipStream_t st, const DevCloud &c, int lds_budget, const float4 *q32,
+                          float4 *g0f, float4 *qmm32, int want_bounds);
+hipError_t launch_gradk_f(hipStream_t st, const DevCloud &c, int lds_budget, const float4 *g0f,
+                          const float4 *gprev, float4 *gnext);
 // stage 0: evaluate only (writes Rout); stages 1..4: residual + SSP-RK stage.
 // q32next (nullable) receives the FP32 shadow of the new q.  lds_budget =
 // bytes of LDS a workgroup may stage its tile image in (tiles with larger

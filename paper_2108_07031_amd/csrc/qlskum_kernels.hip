@@ -458,6 +458,22 @@ __device__ __forceinline__ double lane_group_min(double v) {
     return fmin(v, quad_swap<kQuadXor2>(v));
 }
 
+template <int CTRL>
+__device__ __forceinline__ float quad_swap_f(float v) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ float lane_group_max(float v) {
+    v = fmaxf(v, quad_swap_f<kQuadXor1>(v));
+    return fmaxf(v, quad_swap_f<kQuadXor2>(v));
+}
+
+__device__ __forceinline__ float lane_group_min(float v) {
+    v = fminf(v, quad_swap_f<kQuadXor1>(v));
+    return fminf(v, quad_swap_f<kQuadXor2>(v));
+}
+
 // tile set-up shared by the tiled sweeps: image size ns and whether it is
 // staged (cap = slots that fit the LDS allocation of the launch)
 struct TileInfo {
@@ -747,6 +763,233 @@ __global__ void __launch_bounds__(kBlock) k_gradk(DevCloud cl, int cap,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Mixed-precision q-derivatives.  The same sweeps, tiles and lane layout
+// with the gathered data in FP32 -- q (first pass) or the previous iterate
+// (inner iterations), as FP32 copies -- and the positions in FP64: every
+// offset, difference, product and sum, and the 2x2 solve, stays FP64, and
+// the results are stored in FP32 for the next sweep and the FP32 flux body.
+// Records of 32 and 48 bytes instead of 48 and 80.
+// ---------------------------------------------------------------------------
+namespace {
+
+__device__ __forceinline__ void f4_to_d(float4 a, double v[4]) {
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+
+// first pass over the entries of one point; SRC 0: records in LDS (slot
+// numbers from memory), 2: from memory.  Record: q (float4), position.
+template <int SRC>
+__device__ __forceinline__ void grad0f_entries(const DevCloud &cl, const double2 *lds,
+                                               const float4 *q32, int k0, int k1, int sub,
+                                               const double qp[4], double2 P, double sx[4],
+                                               double sy[4], float mx[4], float mn[4]) {
+    constexpr int kRec = 2;
+#pragma unroll 1
+    for (int k = k0 + sub; k < k1; k += kFluxLanes) {
+        float4 a;
+        double2 Q;
+        if constexpr (SRC == 0) {
+            const double2 *r = lds + kRec * (int)cl.flidx[k];
+            a = *reinterpret_cast<const float4 *>(r);
+            Q = r[1];
+        } else {
+            const int i = cl.idx[k];
+            a = q32[i];
+            Q = cl.xy[i];
+        }
+        const float qf[4] = {a.x, a.y, a.z, a.w};
+        const double dx = Q.x - P.x, dy = Q.y - P.y;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            // the data are FP32, so their bounds are exact in FP32
+            const double dq = (double)qf[r] - qp[r];
+            sx[r] = fma(dx, dq, sx[r]);
+            sy[r] = fma(dy, dq, sy[r]);
+            mx[r] = fmaxf(mx[r], qf[r]);
+            mn[r] = fminf(mn[r], qf[r]);
+        }
+    }
+}
+
+// inner iteration over the entries of one point; SRC as gradk_entries.
+// Record: q_x (float4), q_y (float4), position.
+template <int SRC>
+__device__ __forceinline__ void gradkf_entries(const DevCloud &cl, const double2 *lds,
+                                               const uint16_t *eidx, int e0,
+                                               const float4 *gprev, int kb, int k1, int sub,
+                                               double2 P, double sx[4], double sy[4]) {
+    constexpr int kRec = 3;
+#pragma unroll 1
+    for (int k = kb + sub; k < k1; k += kFluxLanes) {
+        double gi[8];
+        double2 Q;
+        if constexpr (SRC < 2) {
+            const int li = (SRC == 0) ? (int)eidx[k - e0] : (int)cl.flidx[k];
+            const double2 *r = lds + kRec * li;
+            f4_to_d(*reinterpret_cast<const float4 *>(r), gi);
+            f4_to_d(*reinterpret_cast<const float4 *>(r + 1), gi + 4);
+            Q = r[2];
+        } else {
+            const int i = cl.idx[k];
+            f4_to_d(gprev[2 * i], gi);
+            f4_to_d(gprev[2 * i + 1], gi + 4);
+            Q = cl.xy[i];
+        }
+        const double dx = Q.x - P.x, dy = Q.y - P.y;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double f = fma(dx, gi[r], dy * gi[4 + r]);
+            sx[r] = fma(dx, f, sx[r]);
+            sy[r] = fma(dy, f, sy[r]);
+        }
+    }
+}
+
+// components 2 sub, 2 sub + 1 of a point's (q_x[0..3], q_y[0..3]) held as
+// two float4
+__device__ __forceinline__ double2 lane_pair(const float4 *g, int p, int sub) {
+    const float4 a = g[2 * p + (sub >> 1)];
+    return (sub & 1) ? make_double2(a.z, a.w) : make_double2(a.x, a.y);
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) k_grad0_f(DevCloud cl, int cap,
+                                                    const float4 *__restrict__ q32,
+                                                    float4 *__restrict__ g0f,
+                                                    float4 *__restrict__ qmm32, int want_bounds) {
+    constexpr int kRec = 2;
+    extern __shared__ double2 lds[];
+    const int t = logical_block();
+    if (cl.tile_active && !cl.tile_active[t]) return;
+    const TileInfo ti = tile_info(cl, t, cap);
+    if (ti.in_lds) {
+        for (int s0 = threadIdx.x; s0 < ti.ns; s0 += kBlock) {
+            const int p0 = slot_point(cl, ti, s0);
+            if (p0 >= 0) {
+                const float4 a0 = q32[p0];
+                const double2 a1 = cl.xy[p0];
+                *reinterpret_cast<float4 *>(lds + kRec * s0) = a0;
+                lds[kRec * s0 + 1] = a1;
+            }
+        }
+    }
+    __syncthreads();
+    const int j = threadIdx.x / kFluxLanes, sub = threadIdx.x % kFluxLanes;
+    const int p = ti.base + j;
+    double sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
+    float mx[4] = {0, 0, 0, 0}, mn[4] = {0, 0, 0, 0};
+    double qp[4] = {0, 0, 0, 0};
+    if (j < ti.nown) {
+        const float4 a = q32[p];
+        f4_to_d(a, qp);
+        const double2 P = cl.xy[p];
+        mx[0] = mn[0] = a.x;
+        mx[1] = mn[1] = a.y;
+        mx[2] = mn[2] = a.z;
+        mx[3] = mn[3] = a.w;
+        const int k0 = cl.ptr[p], k1 = cl.ptr[p + 1];
+        if (ti.in_lds)
+            grad0f_entries<0>(cl, lds, q32, k0, k1, sub, qp, P, sx, sy, mx, mn);
+        else
+            grad0f_entries<2>(cl, lds, q32, k0, k1, sub, qp, P, sx, sy, mx, mn);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        sx[r] = lane_group_sum(sx[r]);
+        sy[r] = lane_group_sum(sy[r]);
+        mx[r] = lane_group_max(mx[r]);
+        mn[r] = lane_group_min(mn[r]);
+    }
+    if (j >= ti.nown || sub >= 2) return;
+    const double L0 = cl.lsi[3 * p], L1 = cl.lsi[3 * p + 1], L2 = cl.lsi[3 * p + 2];
+    double gv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        gv[r] = (sub == 0) ? fma(L0, sx[r], -(L1 * sy[r])) : fma(L2, sy[r], -(L1 * sx[r]));
+    g0f[2 * p + sub] = to_f4(gv);
+    if (want_bounds) {
+        // bound offsets from q: lane 0 the maxima, lane 1 the minima
+        double bv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bv[r] = (double)(sub == 0 ? mx[r] : mn[r]) - qp[r];
+        qmm32[2 * p + sub] = to_f4(bv);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) k_gradk_f(DevCloud cl, int cap,
+                                                    const float4 *__restrict__ g0f,
+                                                    const float4 *__restrict__ gprev,
+                                                    float4 *__restrict__ gnext) {
+    constexpr int kRec = 3;
+    extern __shared__ double2 lds[];
+    uint16_t *eidx = reinterpret_cast<uint16_t *>(lds + (size_t)kRec * cap);
+    const int t = logical_block();
+    if (cl.tile_active && !cl.tile_active[t]) return;
+    const TileInfo ti = tile_info(cl, t, cap);
+    const int j = threadIdx.x / kFluxLanes, sub = threadIdx.x % kFluxLanes;
+    const int p = ti.base + j;
+    const bool own = j < ti.nown;
+    int kb = 0, k1 = 0;
+    double L0 = 0.0, L1 = 0.0, L2 = 0.0;
+    double2 z = make_double2(0.0, 0.0), gq = make_double2(0.0, 0.0);
+    if (own) {
+        kb = cl.ptr[p];
+        k1 = cl.ptr[p + 1];
+        L0 = cl.lsi[3 * p];
+        L1 = cl.lsi[3 * p + 1];
+        L2 = cl.lsi[3 * p + 2];
+        z = lane_pair(g0f, p, sub);
+        gq = lane_pair(gprev, p, sub);
+    }
+    const int e0 = cl.ptr[ti.base], ne = cl.ptr[ti.base + ti.nown] - e0;
+    const bool e_lds = ti.in_lds && ne <= kCapE;
+    if (ti.in_lds) {
+        for (int s0 = threadIdx.x; s0 < ti.ns; s0 += kBlock) {
+            const int p0 = slot_point(cl, ti, s0);
+            if (p0 >= 0) {
+                const float4 a0 = gprev[2 * p0], a1 = gprev[2 * p0 + 1];
+                const double2 a2 = cl.xy[p0];
+                double2 *d = lds + kRec * s0;
+                *reinterpret_cast<float4 *>(d) = a0;
+                *reinterpret_cast<float4 *>(d + 1) = a1;
+                d[2] = a2;
+            }
+        }
+        if (e_lds)
+            for (int e = threadIdx.x; e < ne; e += kBlock) eidx[e] = cl.flidx[e0 + e];
+    }
+    __syncthreads();
+    double sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
+    if (own) {
+        const double2 P = cl.xy[p];
+        if (e_lds)
+            gradkf_entries<0>(cl, lds, eidx, e0, gprev, kb, k1, sub, P, sx, sy);
+        else if (ti.in_lds)
+            gradkf_entries<1>(cl, lds, eidx, e0, gprev, kb, k1, sub, P, sx, sy);
+        else
+            gradkf_entries<2>(cl, lds, eidx, e0, gprev, kb, k1, sub, P, sx, sy);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        sx[r] = lane_group_sum(sx[r]);
+        sy[r] = lane_group_sum(sy[r]);
+    }
+    if (!own) return;
+    double v[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const int c = 2 * sub + m, r = c & 3;
+        const double ls = (c < 4) ? fma(L0, sx[r], -(L1 * sy[r])) : fma(L2, sy[r], -(L1 * sx[r]));
+        v[m] = fma(-0.5, ls - (m == 0 ? gq.x : gq.y), m == 0 ? z.x : z.y);
+    }
+    // lanes 0,1 and 2,3 hold halves of one float4 (see k_gradk)
+    const double o0 = quad_swap<kQuadXor1>(v[0]), o1 = quad_swap<kQuadXor1>(v[1]);
+    if ((sub & 1) == 0)
+        gnext[2 * p + (sub >> 1)] = make_float4((float)v[0], (float)v[1], (float)o0, (float)o1);
+}
+
 static int lds_cap(const DevCloud &c, int budget, int rec) {
     if (!c.fhalo_ptr) return 0;
     return min(c.fmax_slots, max(budget / rec, 0));
@@ -760,6 +1003,11 @@ static int lds_cap(const DevCloud &c, int budget, int rec) {
 // than 36 KB, although a few more tiles then read from memory).
 constexpr int kGrad0Lds = 32 * 1024;
 constexpr int kGradkLds = 22 * 1024;
+// The FP32-data sweeps fit 64 VGPRs, i.e. 8 waves per SIMD: 8 workgroups
+// per CU when each stays within 20 KB of LDS (images of 32- and 48-byte
+// records; the inner iteration's 4 KB of entry slots come on top).
+constexpr int kGrad0FLds = 20 * 1024;
+constexpr int kGradkFLds = 20 * 1024 - 2 * kCapE;
 
 hipError_t launch_grad0(hipStream_t st, const DevCloud &c, int lds_budget, const double2 *q,
                         double2 *g, double2 *qmm, int want_bounds, Shadow sh) {
@@ -774,6 +1022,26 @@ hipError_t launch_grad0(hipStream_t st, const DevCloud &c, int lds_budget, const
         hipLaunchKernelGGL(k_grad0<true>, dim3(ntile), dim3(kBlock), (size_t)cap * rec, st, c, cap,
                            q, g, qmm, want_bounds, sh);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_grad0_f(hipStream_t st, const DevCloud &c, int lds_budget, const float4 *q32,
+                          float4 *g0f, float4 *qmm32, int want_bounds) {
+    const int rec = 2 * (int)sizeof(double2);
+    const int cap = lds_cap(c, lds_budget > 0 ? lds_budget : kGrad0FLds, rec);
+    hipLaunchKernelGGL(k_grad0_f, dim3(num_flux_tiles(c.n)), dim3(kBlock), (size_t)cap * rec, st,
+                       c, cap, q32, g0f, qmm32, want_bounds);
+    return hipGetLastError();
+}
+
+hipError_t launch_gradk_f(hipStream_t st, const DevCloud &c, int lds_budget, const float4 *g0f,
+                          const float4 *gprev, float4 *gnext) {
+    const int rec = 3 * (int)sizeof(double2);
+    const int cap = min(lds_cap(c, lds_budget > 0 ? lds_budget : kGradkFLds, rec),
+                        (kLdsBytes - 2 * kCapE) / rec);
+    const size_t shmem = cap > 0 ? (size_t)cap * rec + 2 * kCapE : 0;
+    hipLaunchKernelGGL(k_gradk_f, dim3(num_flux_tiles(c.n)), dim3(kBlock), shmem, st, c, cap, g0f,
+                       gprev, gnext);
     return hipGetLastError();
 }
 

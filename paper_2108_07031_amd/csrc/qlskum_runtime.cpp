@@ -78,6 +78,8 @@ struct ql_solver {
     double *U = nullptr, *Un = nullptr, *dt = nullptr, *R = nullptr, *tmp = nullptr;
     double2 *q[2] = {nullptr, nullptr}, *g[3] = {nullptr, nullptr, nullptr}, *qmm = nullptr;
     float4 *q32[2] = {nullptr, nullptr}, *g32 = nullptr, *qmm32 = nullptr;  // FP32 shadows
+    float4 *gf[3] = {nullptr, nullptr, nullptr};  // mixed q-derivatives: first pass, iterates
+    bool grad_f32 = false;  // the last q-derivatives came from the FP32-data sweeps
     double *lsi = nullptr;
     double *Rpart[2] = {nullptr, nullptr};  // [4][n] partial sums of a split flux sweep
     int *fhalo_ptr = nullptr, *fhalo_idx = nullptr;  // tiles of kFluxTile points
@@ -181,6 +183,7 @@ void free_cloud(ql_solver *s) {
     dfree(s->Rpart[1]); dfree(s->errw_outer);
     dfree(s->fhalo_ptr); dfree(s->fhalo_idx); dfree(s->flidx);
     dfree(s->q32[0]); dfree(s->q32[1]); dfree(s->g32); dfree(s->qmm32);
+    dfree(s->gf[0]); dfree(s->gf[1]); dfree(s->gf[2]);
     dfree(s->case_of); dfree(s->chunk_beg); dfree(s->chunk_ptr); dfree(s->ctr);
     dfree(s->dwall_lo); dfree(s->wctr); dfree(s->wsel); dfree(s->wres);
     dfree(s->case_active); dfree(s->tile_active); dfree(s->uinf); dfree(s->part);
@@ -518,19 +521,36 @@ struct Timer {
     }
 };
 
-// One stage's q-derivatives: first pass + n_inner Jacobi iterations; leaves
-// the final iterate in g[gfin].  In mixed precision the flux reads only the
-// FP32 shadows, so unless fp64_out is set (inspection) neither the last
-// iterate's FP64 copy nor the FP64 bounds are written.
-int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds, bool fp64_out) {
-    // the first pass goes to g[2] when inner iterations follow (they read it
-    // as g0); the iterates alternate between g[0] and g[1]
-    const int first = s->prm.n_inner > 0 ? 2 : 0;
-    // mixed precision: the last pass also writes the FP32 shadow of g, the
-    // first pass the FP32 shadow of the bounds
+// One stage's q-derivatives: first pass + n_inner Jacobi iterations.
+// FP64 (and the mixed runs that switch cases to FP64 fluxes): the first
+// pass goes to g[2] when inner iterations follow (they read it as g0), the
+// iterates alternate between g[0] and g[1], the final one is g[gfin]; a
+// switching run also writes the FP32 copies the mixed flux kernel reads.
+// Mixed precision otherwise: the sweeps that gather FP32 data, the first
+// pass into gf[0] (or g32 with no inner iteration), the iterates
+// alternating between gf[1] and gf[2], the last into g32.
+int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds) {
     const bool mixed = s->prm.precision == 1;
-    // a run that switches cases to FP64 fluxes needs both forms
-    const bool skip64 = mixed && !fp64_out && !s->hybrid;
+    s->grad_f32 = mixed && !s->hybrid;
+    if (s->grad_f32) {
+        const int ni = s->prm.n_inner;
+        {
+            Timer t(s, 0);
+            HIPCHK(s, launch_grad0_f(s->stream, c, s->prm.grad_lds, s->q32[s->qcur],
+                                     ni > 0 ? s->gf[0] : s->g32, s->qmm32, want_bounds ? 1 : 0));
+            t.done();
+        }
+        const float4 *cur = s->gf[0];
+        for (int k = 0; k < ni; ++k) {
+            float4 *nxt = (k == ni - 1) ? s->g32 : s->gf[1 + (k & 1)];
+            Timer t(s, 1);
+            HIPCHK(s, launch_gradk_f(s->stream, c, s->prm.grad_lds, s->gf[0], cur, nxt));
+            t.done();
+            cur = nxt;
+        }
+        return QL_OK;
+    }
+    const int first = s->prm.n_inner > 0 ? 2 : 0;
     Shadow sh{nullptr, nullptr, nullptr};
     if (mixed) {
         sh.qmm32 = s->qmm32;
@@ -538,8 +558,7 @@ int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds, bool fp64_o
     }
     {
         Timer t(s, 0);
-        HIPCHK(s, launch_grad0(s->stream, c, s->prm.grad_lds,
-                               s->q[s->qcur], s->g[first], skip64 ? nullptr : s->qmm,
+        HIPCHK(s, launch_grad0(s->stream, c, s->prm.grad_lds, s->q[s->qcur], s->g[first], s->qmm,
                                want_bounds ? 1 : 0, sh));
         t.done();
     }
@@ -549,8 +568,7 @@ int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds, bool fp64_o
         const bool last = k == s->prm.n_inner - 1;
         float4 *g32 = (mixed && last) ? s->g32 : nullptr;
         Timer t(s, 1);
-        HIPCHK(s, launch_gradk(s->stream, c, s->prm.grad_lds,
-                               s->g[2], s->g[cur], (skip64 && last) ? nullptr : s->g[nxt], g32));
+        HIPCHK(s, launch_gradk(s->stream, c, s->prm.grad_lds, s->g[2], s->g[cur], s->g[nxt], g32));
         t.done();
         cur = nxt;
     }
@@ -613,7 +631,7 @@ int enqueue_iteration(ql_solver *s, const DevCloud &c, const FlowParams &fp, int
     for (int rk = 1; rk <= 4; ++rk) {
         int st = QL_OK;
         // the first-order scheme needs no q-derivatives
-        if (fp.order == 2 && (st = run_gradients(s, c, fp.limiter != 0, false))) return st;
+        if (fp.order == 2 && (st = run_gradients(s, c, fp.limiter != 0))) return st;
         Timer t(s, 2);
         st = launch_stage(s, c, fp, rk, rk == 1 ? s->R : nullptr);
         if (st) return st;
@@ -954,6 +972,7 @@ static int upload_impl(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int
     HIPCHK(s, dalloc(&s->qmm, (size_t)4 * n));
     HIPCHK(s, dalloc(&s->q32[0], n)); HIPCHK(s, dalloc(&s->q32[1], n));
     HIPCHK(s, dalloc(&s->g32, (size_t)2 * n)); HIPCHK(s, dalloc(&s->qmm32, (size_t)2 * n));
+    for (int k = 0; k < 3; ++k) HIPCHK(s, dalloc(&s->gf[k], (size_t)2 * n));
     HIPCHK(s, dalloc(&s->fscratch, (size_t)3 * std::max<size_t>(hwall.size(), 1)));
     HIPCHK(s, dalloc(&s->fout, 2)); HIPCHK(s, dalloc(&s->errw, 1));
     HIPCHK(s, dalloc(&s->errw_outer, 1)); HIPCHK(s, dalloc(&s->case_err, ncase));
@@ -1236,7 +1255,7 @@ int ql_evaluate(ql_solver *s) {
     const FlowParams fp = flow_params(s);
     st = reset_err(s);
     if (st) return st;
-    st = run_gradients(s, c, true, true);
+    st = run_gradients(s, c, true);
     if (st) return st;
     st = launch_stage(s, c, fp, 0, s->R);
     if (st) return st;
@@ -1271,6 +1290,14 @@ int ql_debug_fetch(ql_solver *s, int32_t what, double *out) {
         HIPCHK(s, hipMemcpy(h.data(), src, sizeof(double) * count, hipMemcpyDeviceToHost));
         return QL_OK;
     };
+    // FP32 arrays (the mixed q-derivatives and bounds), widened
+    std::vector<float> hf;
+    auto getf = [&](const void *src, size_t count) -> int {
+        hf.resize(count);
+        HIPCHK(s, hipMemcpy(hf.data(), src, sizeof(float) * count, hipMemcpyDeviceToHost));
+        h.assign(hf.begin(), hf.end());
+        return QL_OK;
+    };
     switch (what) {
     case 0:
         if ((st = get(s->q[s->qcur], (size_t)4 * n))) return st;
@@ -1278,7 +1305,8 @@ int ql_debug_fetch(ql_solver *s, int32_t what, double *out) {
             for (int r = 0; r < 4; ++r) out[(size_t)r * n + s->perm[q]] = h[(size_t)4 * q + r];
         break;
     case 1:
-        if ((st = get(s->g[s->gfin], (size_t)8 * n))) return st;
+        if ((st = s->grad_f32 ? getf(s->g32, (size_t)8 * n) : get(s->g[s->gfin], (size_t)8 * n)))
+            return st;
         for (int q = 0; q < n; ++q)
             for (int r = 0; r < 8; ++r) out[(size_t)r * n + s->perm[q]] = h[(size_t)8 * q + r];
         break;
@@ -1293,10 +1321,14 @@ int ql_debug_fetch(ql_solver *s, int32_t what, double *out) {
         break;
     case 4:
     case 5: {
-        // the bounds are held as offsets from q: q + (qmax - q), within an ulp of qmax
-        if ((st = get(s->q[s->qcur], (size_t)4 * n))) return st;
+        // the bounds are held as offsets from q: q + (qmax - q), within an ulp
+        // of qmax (mixed: offsets from the FP32 copy of q, both in FP32)
+        if ((st = s->grad_f32 ? getf(s->q32[s->qcur], (size_t)4 * n)
+                              : get(s->q[s->qcur], (size_t)4 * n)))
+            return st;
         const std::vector<double> hq = h;
-        if ((st = get(s->qmm, (size_t)8 * n))) return st;
+        if ((st = s->grad_f32 ? getf(s->qmm32, (size_t)8 * n) : get(s->qmm, (size_t)8 * n)))
+            return st;
         for (int q = 0; q < n; ++q)
             for (int r = 0; r < 4; ++r)
                 out[(size_t)r * n + s->perm[q]] =
@@ -1351,7 +1383,7 @@ int ql_forces(ql_solver *s, double *cl, double *cd) {
 static int warm_eval(ql_solver *s, const DevCloud &c, const FlowParams &fp) {
     int st = prep_state(s);
     if (st) return st;
-    if ((st = run_gradients(s, c, fp.limiter != 0, false))) return st;
+    if ((st = run_gradients(s, c, fp.limiter != 0))) return st;
     if ((st = launch_stage(s, c, fp, 0, s->R))) return st;
     const Retire off{0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                      nullptr, nullptr, nullptr};
@@ -1537,7 +1569,7 @@ int ql_autotune(ql_solver *s, const char *cache_path, int32_t *chosen) {
                           32 << 10};
     const ql_params saved = s->prm;
     double best_f = 1e30, best_g = 1e30, us = 0.0;
-    if ((st = reset_err(s)) || (st = prep_state(s)) || (st = run_gradients(s, c, fp.limiter != 0, false)))
+    if ((st = reset_err(s)) || (st = prep_state(s)) || (st = run_gradients(s, c, fp.limiter != 0)))
         goto done;
     for (int b : flux_c) {
         s->prm.flux_lds = b;
@@ -1550,7 +1582,7 @@ int ql_autotune(ql_solver *s, const char *cache_path, int32_t *chosen) {
     s->prm.flux_lds = saved.flux_lds;
     for (int b : grad_c) {
         s->prm.grad_lds = b;
-        if ((st = timed([&] { return run_gradients(s, c, fp.limiter != 0, false); }, 3, &us))) goto done;
+        if ((st = timed([&] { return run_gradients(s, c, fp.limiter != 0); }, 3, &us))) goto done;
         if (us < best_g) {
             best_g = us;
             bg = b;

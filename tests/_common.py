@@ -28,6 +28,21 @@ def normwise_rel(a, b):
     return np.abs(a - b).max(axis=1) / den
 
 
+def mixed_g_bound(c, q, g):
+    """Per-row bound (8 rows: q_x then q_y components) on normwise_rel of the
+    mixed path's q-derivatives against FP64 ones.  Their data are q and the
+    iterates rounded to FP32 (relative error <= 2^-24), so each difference
+    q_i - q_p is off by at most 2^-23 max|q| and a least-squares derivative
+    over offsets no shorter than the smallest neighbour distance d_min by
+    about 2^-23 max|q| / d_min; the factor 8 covers the stencils' geometry
+    and the inner iterations (which contract).  q: (4, n), g: (8, n)."""
+    dmin = min(np.hypot(c.x[c.nbr_idx[c.nbr_ptr[p]:c.nbr_ptr[p + 1]]] - c.x[p],
+                        c.y[c.nbr_idx[c.nbr_ptr[p]:c.nbr_ptr[p + 1]]] - c.y[p]).min()
+               for p in range(c.n))
+    qmax = np.abs(q).max(axis=1)
+    return 8.0 * 2.0 ** -23 * np.concatenate([qmax, qmax]) / dmin / np.abs(g).max(axis=1)
+
+
 _CLOUDS = {}
 
 
