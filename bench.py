@@ -318,6 +318,8 @@ def main():
                     help="continue both timed runs (untimed) to N iterations and compare "
                          "mixed with FP64 lift, drag and density (0: skip)")
     ap.add_argument("--no-warm-study", action="store_true")
+    ap.add_argument("--no-fp64-data-mixed", action="store_true",
+                    help="skip the mixed run whose q-derivative sweeps read FP64 data")
     ap.add_argument("--no-batch-study", action="store_true")
     ap.add_argument("--precision", choices=("both", "fp64", "mixed"), default="both")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="naca2.5m",
@@ -352,19 +354,20 @@ def main():
     stream = torch.cuda.Stream()  # default priority
     torch.cuda.set_stream(stream)
 
-    def timed_run(precision):
+    def timed_run(precision, mixed_grad=0):
         t_up = time.perf_counter()
-        split = dict(flux_split=args.flux_split) if precision == 0 else {}
+        split = dict(flux_split=args.flux_split) if precision == 0 else dict(mixed_grad=mixed_grad)
         s = ql.Solver(cloud, stream=stream, precision=precision, reorder=reorder, **split, **FLOW)
-        log(f"[{PREC_NAME[precision]}] upload {time.perf_counter() - t_up:.1f} s")
+        label = PREC_NAME[precision] + (", FP64-data q-derivatives" if mixed_grad else "")
+        log(f"[{label}] upload {time.perf_counter() - t_up:.1f} s")
         flags = s.flags()
         s.init_freestream()
-        log(f"[{PREC_NAME[precision]}] warmup {args.warmup}")
+        log(f"[{label}] warmup {args.warmup}")
         s.step(args.warmup, want_history=False)
         ql.ql_set_timing(s.h, 1)
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        log(f"[{PREC_NAME[precision]}] timed: {args.steps} iterations")
+        log(f"[{label}] timed: {args.steps} iterations")
         wall0 = time.perf_counter()
         ev0.record(stream)
         hist = s.step(args.steps)
@@ -374,7 +377,7 @@ def main():
         gpu_ms = ev0.elapsed_time(ev1)
         ktime = {k: ql.ql_kernel_time(s.h, k) for k in range(4)}
         ql.ql_set_timing(s.h, 0)
-        log(f"[{PREC_NAME[precision]}] wall {wall:.3f} s, events {gpu_ms / 1e3:.3f} s, "
+        log(f"[{label}] wall {wall:.3f} s, events {gpu_ms / 1e3:.3f} s, "
             f"residual {hist[0, 0]:.3e} -> {hist[-1, 0]:.3e}")
         for k, name in enumerate(("grad0", "gradk", "flux", "resnorm")):
             ms, cnt = ktime[k]
@@ -387,7 +390,7 @@ def main():
             # the same run continued (untimed) to a fixed iteration count, for
             # the FP64 vs mixed comparison of lift, drag and density
             if more > 0:
-                log(f"[{PREC_NAME[precision]}] continued to {args.accuracy_iters} iterations")
+                log(f"[{label}] continued to {args.accuracy_iters} iterations")
                 s.step(more, want_history=False)
             acc = dict(iterations=max(args.accuracy_iters, args.warmup + args.steps),
                        cl_cd=s.forces(), rho=s.fetch_state()[0].copy())
@@ -407,6 +410,9 @@ def main():
 
     runs = {p: timed_run(p) for p in ((0, 1) if args.precision == "both" else
                                       (0,) if args.precision == "fp64" else (1,))}
+    if args.precision == "both" and not args.no_fp64_data_mixed:
+        # the mixed path with FP64-data q-derivative sweeps, for comparison
+        runs["mixed_grad1"] = timed_run(1, mixed_grad=1)
     head = runs[0] if 0 in runs else runs[1]
     flops = flux_flops_per_launch(head["flags"], cloud.kind, cloud.nbr_ptr, FLOW["limiter"])
     flux_ms, flux_cnt = head["ktime"][2]
@@ -451,18 +457,28 @@ def main():
         out["mixed"] = {"value": runs[1]["value"], "unit": "Mpoint-iter/s",
                         "ms_per_step": runs[1]["elapsed"] * 1e3 / args.steps,
                         "over_fp64": runs[1]["value"] / runs[0]["value"],
-                        "dtype": "f32 flux body, f64 sums and update"}
-        a0, a1 = runs[0]["acc"], runs[1]["acc"]
-        if a0 and a1:
+                        "dtype": "f32 flux body and q-derivative data; f64 q-derivative "
+                                 "arithmetic, sums and update"}
+
+        def vs_fp64(a0, a1):
             # mixed vs FP64 from the same freestream start after the same
             # number of iterations (the configuration's 1000)
-            out["mixed"]["vs_fp64"] = {
-                "iterations": a0["iterations"],
-                "cl_cd_fp64": list(a0["cl_cd"]), "cl_cd_mixed": list(a1["cl_cd"]),
-                "abs_dcl": abs(a1["cl_cd"][0] - a0["cl_cd"][0]),
-                "abs_dcd": abs(a1["cl_cd"][1] - a0["cl_cd"][1]),
-                "density_max_rel": float(np.abs(a1["rho"] - a0["rho"]).max()
-                                         / np.abs(a0["rho"]).max())}
+            return {"iterations": a0["iterations"],
+                    "cl_cd_fp64": list(a0["cl_cd"]), "cl_cd_mixed": list(a1["cl_cd"]),
+                    "abs_dcl": abs(a1["cl_cd"][0] - a0["cl_cd"][0]),
+                    "abs_dcd": abs(a1["cl_cd"][1] - a0["cl_cd"][1]),
+                    "density_max_rel": float(np.abs(a1["rho"] - a0["rho"]).max()
+                                             / np.abs(a0["rho"]).max())}
+        if runs[0]["acc"] and runs[1]["acc"]:
+            out["mixed"]["vs_fp64"] = vs_fp64(runs[0]["acc"], runs[1]["acc"])
+        if "mixed_grad1" in runs:
+            r = runs["mixed_grad1"]
+            out["mixed"]["fp64_data_q_derivatives"] = {
+                "value": r["value"], "ms_per_step": r["elapsed"] * 1e3 / args.steps,
+                "over_fp64": r["value"] / runs[0]["value"]}
+            if runs[0]["acc"] and r["acc"]:
+                out["mixed"]["fp64_data_q_derivatives"]["vs_fp64"] = vs_fp64(runs[0]["acc"],
+                                                                              r["acc"])
     if not headline:
         args.no_batch_study = args.no_warm_study = args.no_cpu_baseline = True
     if not args.no_batch_study:

@@ -72,7 +72,8 @@ typedef struct {
     double venkat_k;  /* limiter constant K, eps^2 = (K |P_i - P|)^3            */
     int32_t precision;/* 0 FP64 throughout; 1 mixed: reconstruction, limiter
                          and split fluxes in FP32, least-squares weights,
-                         residual sums and the state update in FP64           */
+                         residual sums and the state update in FP64; the
+                         q-derivatives in FP64 arithmetic (see mixed_grad)   */
     int32_t reorder;  /* read at upload: 0 caller order, 1 Hilbert curve,
                        * 2 reverse Cuthill-McKee on the neighbour graph      */
     int32_t flux_lds; /* tuning: bytes of LDS in which a flux workgroup stages
@@ -80,7 +81,9 @@ typedef struct {
                          do not fit read from memory; same results either
                          way); 0 = the library's default, at most 163840      */
     int32_t grad_lds; /* tuning: the same for the q-derivative sweeps (records
-                         of 48 and 80 bytes); 0 = default, at most 163840     */
+                         of 48 and 80 bytes; 32 and 48 for the FP32-data
+                         sweeps of mixed_grad 0); 0 = default, at most
+                         163840                                               */
     int32_t order;    /* 2: second order, the split fluxes of the modified q
                          of eq. (28) (sec. 2.1); 1: first-order LSKUM, the
                          split fluxes of q itself (sec. 2; no q-derivatives
@@ -107,7 +110,15 @@ typedef struct {
                          count in the residual norm.  Needs non-singular
                          s+, s-, n+ stencils at every outer point
                          (QL_ESINGULAR otherwise, at upload or here)      */
-    int32_t pad0;     /* reserved, 0                                           */
+    int32_t mixed_grad;/* precision 1: data of the q-derivative sweeps (whose
+                         sums and 2x2 solves are FP64 either way).  0: FP32
+                         copies of q and of the inner iterates, widened to
+                         FP64: the first pass is then the exact least-squares
+                         derivative of the FP32 q that the flux body
+                         reconstructs from, and each iterate is rounded to
+                         FP32 (2^-24 relative) before the next uses it;
+                         1: FP64 q and iterates, as in precision 0.
+                         ql_batch_run with mixed_switch > 0 uses 1          */
     double mixed_switch; /* precision 1 in ql_batch_run: a case whose density
                          residual norm falls to mixed_switch x its reference
                          continues with FP64 split fluxes (the FP32 flux body

@@ -424,6 +424,8 @@ int check_params(ql_solver *s, const ql_params *p) {
     if (p->flux_split < 0 || p->flux_split > 2)
         return fail(s, QL_EINVAL, "flux_split must be 0, 1 or 2");
     if (p->outer_bc != 0 && p->outer_bc != 1) return fail(s, QL_EINVAL, "outer_bc must be 0 or 1");
+    if (p->mixed_grad != 0 && p->mixed_grad != 1)
+        return fail(s, QL_EINVAL, "mixed_grad must be 0 or 1");
     if (!(p->mixed_switch >= 0.0 && p->mixed_switch < 1.0))
         return fail(s, QL_EINVAL, "mixed_switch must lie in [0, 1)");
     if (p->outer_bc == 1 && s->has_cloud && s->outer_bad >= 0)
@@ -522,16 +524,18 @@ struct Timer {
 };
 
 // One stage's q-derivatives: first pass + n_inner Jacobi iterations.
-// FP64 (and the mixed runs that switch cases to FP64 fluxes): the first
-// pass goes to g[2] when inner iterations follow (they read it as g0), the
-// iterates alternate between g[0] and g[1], the final one is g[gfin]; a
-// switching run also writes the FP32 copies the mixed flux kernel reads.
-// Mixed precision otherwise: the sweeps that gather FP32 data, the first
-// pass into gf[0] (or g32 with no inner iteration), the iterates
-// alternating between gf[1] and gf[2], the last into g32.
-int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds) {
+// Mixed precision with FP32 data (mixed_grad 0, no precision switch): the
+// sweeps that gather FP32 copies, the first pass into gf[0] (or g32 with no
+// inner iteration), the iterates alternating between gf[1] and gf[2], the
+// last into g32.  Otherwise the FP64 sweeps: the first pass goes to g[2]
+// when inner iterations follow (they read it as g0), the iterates alternate
+// between g[0] and g[1], the final one is g[gfin]; in mixed precision they
+// also write the FP32 copies the mixed flux sweep reads, and skip the FP64
+// bounds and final iterate that only inspection (fp64_out) or a run that
+// switches cases to FP64 fluxes reads.
+int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds, bool fp64_out) {
     const bool mixed = s->prm.precision == 1;
-    s->grad_f32 = mixed && !s->hybrid;
+    s->grad_f32 = mixed && !s->hybrid && s->prm.mixed_grad == 0;
     if (s->grad_f32) {
         const int ni = s->prm.n_inner;
         {
@@ -551,6 +555,7 @@ int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds) {
         return QL_OK;
     }
     const int first = s->prm.n_inner > 0 ? 2 : 0;
+    const bool skip64 = mixed && !fp64_out && !s->hybrid;
     Shadow sh{nullptr, nullptr, nullptr};
     if (mixed) {
         sh.qmm32 = s->qmm32;
@@ -558,8 +563,8 @@ int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds) {
     }
     {
         Timer t(s, 0);
-        HIPCHK(s, launch_grad0(s->stream, c, s->prm.grad_lds, s->q[s->qcur], s->g[first], s->qmm,
-                               want_bounds ? 1 : 0, sh));
+        HIPCHK(s, launch_grad0(s->stream, c, s->prm.grad_lds, s->q[s->qcur], s->g[first],
+                               skip64 ? nullptr : s->qmm, want_bounds ? 1 : 0, sh));
         t.done();
     }
     int cur = first;
@@ -568,7 +573,8 @@ int run_gradients(ql_solver *s, const DevCloud &c, bool want_bounds) {
         const bool last = k == s->prm.n_inner - 1;
         float4 *g32 = (mixed && last) ? s->g32 : nullptr;
         Timer t(s, 1);
-        HIPCHK(s, launch_gradk(s->stream, c, s->prm.grad_lds, s->g[2], s->g[cur], s->g[nxt], g32));
+        HIPCHK(s, launch_gradk(s->stream, c, s->prm.grad_lds, s->g[2], s->g[cur],
+                               (skip64 && last) ? nullptr : s->g[nxt], g32));
         t.done();
         cur = nxt;
     }
@@ -631,7 +637,7 @@ int enqueue_iteration(ql_solver *s, const DevCloud &c, const FlowParams &fp, int
     for (int rk = 1; rk <= 4; ++rk) {
         int st = QL_OK;
         // the first-order scheme needs no q-derivatives
-        if (fp.order == 2 && (st = run_gradients(s, c, fp.limiter != 0))) return st;
+        if (fp.order == 2 && (st = run_gradients(s, c, fp.limiter != 0, false))) return st;
         Timer t(s, 2);
         st = launch_stage(s, c, fp, rk, rk == 1 ? s->R : nullptr);
         if (st) return st;
@@ -763,7 +769,7 @@ void ql_default_params(ql_params *p) {
     p->order = 2;
     p->flux_split = 0;
     p->outer_bc = 0;
-    p->pad0 = 0;
+    p->mixed_grad = 0;
     p->mixed_switch = 0.0;
 }
 
@@ -1255,7 +1261,7 @@ int ql_evaluate(ql_solver *s) {
     const FlowParams fp = flow_params(s);
     st = reset_err(s);
     if (st) return st;
-    st = run_gradients(s, c, true);
+    st = run_gradients(s, c, true, true);
     if (st) return st;
     st = launch_stage(s, c, fp, 0, s->R);
     if (st) return st;
@@ -1383,7 +1389,7 @@ int ql_forces(ql_solver *s, double *cl, double *cd) {
 static int warm_eval(ql_solver *s, const DevCloud &c, const FlowParams &fp) {
     int st = prep_state(s);
     if (st) return st;
-    if ((st = run_gradients(s, c, fp.limiter != 0))) return st;
+    if ((st = run_gradients(s, c, fp.limiter != 0, false))) return st;
     if ((st = launch_stage(s, c, fp, 0, s->R))) return st;
     const Retire off{0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                      nullptr, nullptr, nullptr};
@@ -1569,7 +1575,7 @@ int ql_autotune(ql_solver *s, const char *cache_path, int32_t *chosen) {
                           32 << 10};
     const ql_params saved = s->prm;
     double best_f = 1e30, best_g = 1e30, us = 0.0;
-    if ((st = reset_err(s)) || (st = prep_state(s)) || (st = run_gradients(s, c, fp.limiter != 0)))
+    if ((st = reset_err(s)) || (st = prep_state(s)) || (st = run_gradients(s, c, fp.limiter != 0, false)))
         goto done;
     for (int b : flux_c) {
         s->prm.flux_lds = b;
@@ -1582,7 +1588,7 @@ int ql_autotune(ql_solver *s, const char *cache_path, int32_t *chosen) {
     s->prm.flux_lds = saved.flux_lds;
     for (int b : grad_c) {
         s->prm.grad_lds = b;
-        if ((st = timed([&] { return run_gradients(s, c, fp.limiter != 0); }, 3, &us))) goto done;
+        if ((st = timed([&] { return run_gradients(s, c, fp.limiter != 0, false); }, 3, &us))) goto done;
         if (us < best_g) {
             best_g = us;
             bg = b;

@@ -44,7 +44,7 @@ class ql_params(C.Structure):
                 ("cfl", C.c_double), ("n_inner", C.c_int32), ("limiter", C.c_int32),
                 ("venkat_k", C.c_double), ("precision", C.c_int32), ("reorder", C.c_int32),
                 ("flux_lds", C.c_int32), ("grad_lds", C.c_int32), ("order", C.c_int32),
-                ("flux_split", C.c_int32), ("outer_bc", C.c_int32), ("pad0", C.c_int32),
+                ("flux_split", C.c_int32), ("outer_bc", C.c_int32), ("mixed_grad", C.c_int32),
                 ("mixed_switch", C.c_double)]
 
 

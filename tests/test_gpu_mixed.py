@@ -73,6 +73,37 @@ def test_mixed_evaluate_close_to_oracle(ql, limiter):
     s32.close()
 
 
+@pytest.mark.parametrize("limiter", [0, 1])
+def test_mixed_grad_fp64_data(ql, limiter):
+    """mixed_grad 1: the q-derivative sweeps read FP64 data, so the mixed
+    path's q-derivatives equal the FP64 path's bit for bit (both run the FP64
+    sweeps); R within the evaluation bound of the oracle, and 20 iterations
+    within 1e-5 of those with FP32-data sweeps (mixed_grad 0)."""
+    _say(f"mixed_grad 1 limiter={limiter}")
+    c = cloud("jitter")
+    prm = dict(limiter=limiter, mach=0.85 if limiter else 0.63, alpha_deg=1.0 if limiter else 2.0)
+    U = smooth_state(c, mach=prm["mach"], alpha_deg=prm["alpha_deg"])
+    ora = oracle.Oracle(c, oracle.params(**prm)).evaluate(U)
+    s64 = ql.Solver(c, precision=0, **prm)
+    s64.set_state(U)
+    e64 = s64.evaluate()
+    s64.close()
+    out = {}
+    for mg in (0, 1):
+        s = ql.Solver(c, precision=1, mixed_grad=mg, **prm)
+        s.set_state(U)
+        out[mg] = s.evaluate()
+        s.set_state(U)
+        s.step(20, want_history=False)
+        out[mg]["U20"] = s.fetch_state()
+        s.close()
+    np.testing.assert_array_equal(out[1]["g"], e64["g"])
+    assert np.all(normwise_rel(out[1]["R"], ora["R"]) <= 2e-3)
+    d = normwise_rel(out[0]["U20"], out[1]["U20"])
+    _say(f"  20 iterations, FP32- vs FP64-data sweeps: {d.max():.2e}")
+    assert np.all(d <= 1e-5), d
+
+
 def test_mixed_converged_forces(ql):
     """9,600-point cloud, M 0.63, alpha 2, from the freestream: the FP64 path
     brings the density residual six decades below its first value within
