@@ -50,6 +50,15 @@ def build_omp():
     return build(cflags=("-O2", "-ffp-contract=off", "-fopenmp"), out=OMP_LIB)
 
 
+OMP_FMA_LIB = os.path.join(_HERE, "liboracle_omp_fma.so")
+
+
+def build_omp_fma():
+    """The FMA-contracted build with OpenMP: the noise-floor reference of
+    build_fma() for runs on whole large clouds."""
+    return build(cflags=("-O2", "-mfma", "-ffp-contract=fast", "-fopenmp"), out=OMP_FMA_LIB)
+
+
 class OracleError(RuntimeError):
     def __init__(self, code, point):
         super().__init__(f"oracle status {code} at point {point}")
@@ -89,6 +98,8 @@ def load(path=_LIB):
             build_fma()
         elif path == OMP_LIB:
             build_omp()
+        elif path == OMP_FMA_LIB:
+            build_omp_fma()
         else:
             raise FileNotFoundError(path)
     lib = C.CDLL(path)

@@ -303,6 +303,39 @@ def test_c2_sampled_iteration(ql):
     _sampled_iteration_check(c, U, U1, prm, seed=17)
 
 
+@pytest.mark.timeout(600)
+def test_c2_full_size_ten_iterations(ql):
+    """2.5M-point cloud in the benchmark's configuration (M 0.85, alpha 1,
+    limiter K 5), 10 whole iterations from a smooth state on every point:
+    the GPU state and residual history against the oracle's (its OpenMP
+    build, bit for bit the serial one), within 10x the distance between the
+    oracle and its FMA-contracted build after the same 10 iterations (the
+    history also within the bound of a reordered sum of n squares)."""
+    _say("c2 full size, 10 iterations")
+    c = cloud("c2")
+    prm = dict(limiter=1, mach=0.85, alpha_deg=1.0)
+    U0 = smooth_state(c, mach=0.85, alpha_deg=1.0)
+    s = ql.Solver(c, **prm)
+    s.set_state(U0)
+    hist = s.step(10)
+    U = s.fetch_state()
+    s.close()
+    Uo, ho = oracle.Oracle(c, oracle.params(**prm), lib=oracle.load(oracle.OMP_LIB)).run(U0, 10)
+    _say("  oracle done")
+    Uf, hf = oracle.Oracle(c, oracle.params(**prm),
+                           lib=oracle.load(oracle.OMP_FMA_LIB)).run(U0, 10)
+    floor = normwise_rel(Uf, Uo)
+    err = normwise_rel(U, Uo)
+    hfloor = np.abs(hf - ho).max() / np.abs(ho).max()
+    herr = np.abs(hist - ho).max() / np.abs(ho).max()
+    _say(f"  state: gpu {err.max():.2e}  floor {floor.max():.2e}; "
+         f"history: gpu {herr:.2e}  floor {hfloor:.2e}")
+    assert np.all(err <= 10.0 * floor + 1e-15), (err, floor)
+    # the norms' sums over n squares run in another order on the GPU: a
+    # relative difference of at most about n u (u = 2^-53) on top
+    assert herr <= 10.0 * hfloor + c.n * 2.0 ** -53, (herr, hfloor)
+
+
 @pytest.mark.skipif(not os.environ.get("QL_NACA40M"),
                     reason="the 40M-point cloud takes minutes to build; set QL_NACA40M to a "
                            ".npz path (the cloud is cached there) to run this check")

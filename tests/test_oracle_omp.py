@@ -51,3 +51,18 @@ def test_same_failing_point(libs):
         with pytest.raises(oracle.OracleError) as e:
             o.evaluate(U)
         assert e.value.code == oracle.EPOSITIVITY and e.value.point == min(bad)
+
+
+def test_fma_builds_bitwise_equal():
+    """The OpenMP build of the FMA-contracted oracle (the noise-floor
+    reference of the full-size GPU checks) gives the serial FMA build's
+    results bit for bit."""
+    oracle.build_omp_fma()
+    ser, omp = oracle.load(oracle.FMA_LIB), oracle.load(oracle.OMP_FMA_LIB)
+    c = cloud("jitter")
+    prm = oracle.params(limiter=1, mach=0.85, alpha_deg=1.0)
+    U0 = smooth_state(c, mach=0.85, alpha_deg=1.0)
+    Ua, ha = oracle.Oracle(c, prm, lib=ser).run(U0, 5)
+    Ub, hb = oracle.Oracle(c, prm, lib=omp).run(U0, 5)
+    np.testing.assert_array_equal(Ua, Ub)
+    np.testing.assert_array_equal(ha, hb)
