@@ -155,17 +155,9 @@ BATCH = dict(n_case=64, n_lo=40000, n_hi=640000, seed=7031, iters=200, precision
 
 def batch_study():
     import torch
-    from cloudgen import naca_ocloud, sample_conditions, uniform01
     from paper_2108_07031_amd import qlskum as ql
     B = BATCH
-    u = uniform01(B["seed"], B["n_case"])
-    sizes = np.exp(np.log(B["n_lo"]) + u * (np.log(B["n_hi"]) - np.log(B["n_lo"])))
-    conds = sample_conditions(B["seed"] + 1, B["n_case"], mach=(0.3, 0.85))
-    clouds = []
-    for k, (nn, c) in enumerate(zip(sizes, conds)):
-        ns = 2 * int(round(np.sqrt(5.0 * nn / 8.0) / 2))  # Ns:Nr = 5:8, Ns even
-        clouds.append(naca_ocloud(ns, int(round(nn / ns)), tau=c["tau"], jitter=0.1,
-                                  seed=B["seed"] + 10 + k))
+    conds, clouds = _batch_clouds(1)
     total = sum(cl.n for cl in clouds)
     prm = dict(limiter=1, precision=B["precision"])
     log(f"  {B['n_case']} clouds, {total} points")
@@ -195,6 +187,85 @@ def batch_study():
             "batched_mpt_it_s": total * B["iters"] / t_batch / 1e6,
             "sequential_mpt_it_s": total * B["iters"] / t_solo / 1e6,
             "speedup": t_solo / t_batch}
+
+
+def _batch_clouds(scale):
+    """The batched study's 64 conditions and clouds, sizes divided by scale."""
+    from cloudgen import naca_ocloud, sample_conditions, uniform01
+    B = BATCH
+    u = uniform01(B["seed"], B["n_case"])
+    lo, hi = B["n_lo"] / scale, B["n_hi"] / scale
+    sizes = np.exp(np.log(lo) + u * (np.log(hi) - np.log(lo)))
+    conds = sample_conditions(B["seed"] + 1, B["n_case"], mach=(0.3, 0.85))
+    clouds = []
+    for k, (nn, c) in enumerate(zip(sizes, conds)):
+        ns = 2 * int(round(np.sqrt(5.0 * nn / 8.0) / 2))  # Ns:Nr = 5:8, Ns even
+        clouds.append(naca_ocloud(ns, int(round(nn / ns)), tau=c["tau"], jitter=0.1,
+                                  seed=B["seed"] + 10 + k))
+    return conds, clouds
+
+
+def batch_drop_study(scale, max_iter, check_every=500, switch=3e-5, sequential=True):
+    """The batched form run to each case's 1e-6 drop of its first residual:
+    mixed precision with the precision switch, one batch (captured iteration
+    replayed, per-case retirement on the device) against the same cases run
+    one after the other the same way; clouds scale x smaller than the
+    throughput study's."""
+    import torch
+    from paper_2108_07031_amd import qlskum as ql
+    conds, clouds = _batch_clouds(scale)
+    total = sum(cl.n for cl in clouds)
+    prm = dict(limiter=1, precision=1, mixed_switch=switch)
+    log(f"  to the drop: {len(clouds)} clouds, {total} points")
+    s = ql.Solver(**prm)
+    s.upload_batch(clouds, [c["mach"] for c in conds], [c["alpha"] for c in conds])
+    s.init_freestream()
+    seen = {"active": len(clouds), "t0": 0.0}
+
+    def progress(it, active, every=10000):
+        # from the batched run's own check windows
+        if active != seen["active"] or it % every == 0:
+            log(f"    iteration {it}: {active} cases active "
+                f"({time.perf_counter() - seen['t0']:.1f} s)")
+            seen["active"] = active
+    s.set_progress(progress)
+    torch.cuda.synchronize()
+    t0 = seen["t0"] = time.perf_counter()
+    iters, _ = s.batch_run(1e-6, max_iter, check_every=check_every)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    sw = s.batch_switched()
+    status = s.batch_status()
+    s.close()
+    log(f"  batched: {t_batch:.1f} s, iterations {int(iters.min())}..{int(iters.max())}")
+    t_solo, iters_solo = 0.0, []
+    for k, (cl, c) in enumerate(zip(clouds, conds) if sequential else ()):
+        so = ql.Solver(cl, mach=c["mach"], alpha_deg=c["alpha"], **prm)
+        so.init_freestream()
+        so.set_progress(lambda it, active, k=k: it % 20000 == 0 and
+                        log(f"    case {k}: iteration {it}"))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, _ = so.batch_run(1e-6, max_iter, check_every=check_every)
+        torch.cuda.synchronize()
+        t_solo += time.perf_counter() - t0
+        iters_solo.append(int(it[0]))
+        so.close()
+        if k % 8 == 7:
+            log(f"  one after the other: {k + 1} cases, {t_solo:.1f} s")
+    work = float(sum(cl.n * int(i) for cl, i in zip(clouds, iters)))
+    return {"cases": len(clouds), "points_total": total, "scale": scale,
+            "points_min_max": [min(cl.n for cl in clouds), max(cl.n for cl in clouds)],
+            "precision": "mixed, switch to FP64 fluxes at 3e-5 of the first residual",
+            "drop": 1e-6, "max_iter": max_iter,
+            "reached": int(sum(1 for st, i in zip(status, iters)
+                               if st == ql.QL_OK and i < max_iter)),
+            "iterations": [int(i) for i in iters], "iterations_solo": iters_solo,
+            "switched_after": [int(i) for i in sw],
+            "wall_batched_s": t_batch, "wall_sequential_s": t_solo if sequential else None,
+            "batched_mpt_it_s": work / t_batch / 1e6,
+            "sequential_mpt_it_s": work / t_solo / 1e6 if sequential else None,
+            "speedup": t_solo / t_batch if sequential else None}
 
 
 def _prims(U, gamma=1.4):
@@ -305,6 +376,132 @@ def warm_study():
     }
 
 
+# A larger warm-start study: the C3 sampler's Mach range, 128 training
+# conditions on 10k-point clouds and 16 held-out ones on 40k-point clouds,
+# every solve a batch in mixed precision with the precision switch.
+WARM_LARGE = dict(ns=80, nr=128, ns_test=160, nr_test=256, n_train=128, n_test=16, seed_train=1,
+                  seed_test=2, mach=(0.3, 0.85), drop=1e-6, max_iter=150000,
+                  widths=[6, 128, 128, 128, 128, 4], steps=8000, batch=8192, lr=2e-3, floor=0.05,
+                  switch=3e-5)
+
+
+def _features(clouds, conds, d, offs):
+    from cloudgen import warm_features
+    return np.concatenate([warm_features(cl, d[offs[i]:offs[i + 1]], c["mach"], c["alpha"],
+                                         c["tau"]) for i, (cl, c) in enumerate(zip(clouds, conds))])
+
+
+def warm_study_large():
+    """Training data from one batched solve; the held-out cases solved cold
+    as one batch and warm (inference, per-case fallback, then the run) as
+    another, with the same reference (the freestream's first residual); a
+    held-out case counts when its cold run reaches the drop."""
+    import torch
+    from cloudgen import glorot_weights, naca_ocloud, sample_conditions, uniform01
+    from paper_2108_07031_amd import qlskum as ql
+    W = WARM_LARGE
+    t_all = time.perf_counter()
+    prm = dict(limiter=1, precision=1, mixed_switch=W["switch"])
+    train = sample_conditions(W["seed_train"], W["n_train"], mach=W["mach"])
+    test = sample_conditions(W["seed_test"], W["n_test"], mach=W["mach"])
+    # jittered like the throughput clouds (the unjittered generator cannot
+    # repair every trailing-edge stencil at these resolutions)
+    clouds = [naca_ocloud(W["ns"], W["nr"], tau=c["tau"], jitter=0.1, seed=100 + k)
+              for k, c in enumerate(train)]
+    tclouds = [naca_ocloud(W["ns_test"], W["nr_test"], tau=c["tau"], jitter=0.1, seed=1000 + k)
+               for k, c in enumerate(test)]
+
+    def progress(tag):
+        seen = {"active": None}
+
+        def fn(it, active):
+            if active != seen["active"] or it % 20000 == 0:
+                log(f"    {tag}: iteration {it}, {active} cases active")
+                seen["active"] = active
+        return fn
+    s = ql.Solver(**prm)
+    offs = s.upload_batch(clouds, [c["mach"] for c in train], [c["alpha"] for c in train])
+    s.set_progress(progress("training solve"))
+    s.init_freestream()
+    t0 = time.perf_counter()
+    it_train, _ = s.batch_run(W["drop"], W["max_iter"], check_every=500)
+    t_conv = time.perf_counter() - t0
+    ok_case = (s.batch_status() == ql.QL_OK) & (np.asarray(it_train) < W["max_iter"])
+    U = s.fetch_state()
+    d = s.wall_distance()
+    s.close()
+    F = _features(clouds, train, d, offs)
+    keep = (np.concatenate([cl.kind for cl in clouds]) != 2) & np.repeat(
+        ok_case, [cl.n for cl in clouds])
+    F, P = F[keep], _prims(U)[keep]
+    fm, fs = F.mean(axis=0), F.std(axis=0) + 1e-12
+    pm, ps = P.mean(axis=0), P.std(axis=0) + 1e-12
+    X = torch.tensor((F - fm) / fs, dtype=torch.float32, device="cuda")
+    Y = torch.tensor((P - pm) / ps, dtype=torch.float32, device="cuda")
+    log(f"  training net on {X.shape[0]} samples from {int(ok_case.sum())} converged cases")
+    m = ql.Mlp(W["widths"], max_batch=W["batch"])
+    m.set_weights(glorot_weights(W["widths"], 2108))
+    nb = X.shape[0] // W["batch"]
+    order = torch.tensor(np.argsort(uniform01(31, X.shape[0] * 8).reshape(8, -1), axis=1),
+                         device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = None
+    for step in range(W["steps"]):
+        ep, b = divmod(step, max(nb, 1))
+        idx = order[ep % 8, b * W["batch"]:(b + 1) * W["batch"]]
+        lr = W["lr"] * (0.1 if step >= 0.75 * W["steps"] else 1.0)
+        loss = m.train_step(X[idx].contiguous(), Y[idx].contiguous(), lr,
+                            want_loss=(step == W["steps"] - 1))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del X, Y
+    mach, alpha = [c["mach"] for c in test], [c["alpha"] for c in test]
+    sc = ql.Solver(**prm)
+    toffs = sc.upload_batch(tclouds, mach, alpha)
+    sc.set_progress(progress("held-out cold"))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sc.init_freestream()
+    ic, _ = sc.batch_run(W["drop"], W["max_iter"], check_every=500)
+    t_cold = time.perf_counter() - t0
+    st_cold = sc.batch_status()
+    dw = sc.wall_distance()
+    sc.close()
+    sw = ql.Solver(**prm)
+    sw.upload_batch(tclouds, mach, alpha)
+    sw.set_progress(progress("held-out warm"))
+    Xc = torch.tensor((_features(tclouds, test, dw, toffs) - fm) / fs, dtype=torch.float32,
+                      device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rcold, rwarm, used = sw.warm_start(m, Xc, np.concatenate([pm, ps]), W["floor"])
+    iw, _ = sw.batch_run(W["drop"], W["max_iter"], check_every=500, ref=rcold[:, 0])
+    t_warm = time.perf_counter() - t0
+    st_warm = sw.batch_status()
+    sw.close()
+    m.close()
+    ok = [(st_cold[k] == ql.QL_OK and ic[k] < W["max_iter"]) for k in range(W["n_test"])]
+    ratios = [iw[k] / ic[k] for k in range(W["n_test"]) if ok[k]]
+    return {
+        "cases_train": W["n_train"], "points_per_train_case": clouds[0].n,
+        "cases_test": W["n_test"], "points_per_test_case": tclouds[0].n,
+        "mach_range": list(W["mach"]), "drop": W["drop"], "max_iter": W["max_iter"],
+        "precision": "mixed, switch to FP64 fluxes at 3e-5 of the first residual",
+        "train_converged": int(np.sum(ok_case)), "train_samples": int(keep.sum()),
+        "train_solve_s": t_conv, "train_net_s": t_train, "train_loss": loss,
+        "network": "6-128x4-4 tanh, bf16 MFMA, FP32 accumulate, Adam",
+        "test_cold_reached": int(sum(ok)),
+        "iters_cold": [int(i) for i in ic], "iters_warm": [int(i) for i in iw],
+        "status_warm": [int(x) for x in st_warm], "used": [bool(u) for u in used],
+        "iters_ratio_median": float(np.median(ratios)) if ratios else None,
+        "wall_cold_batch_s": t_cold, "wall_warm_batch_s": t_warm,
+        "wall_ratio_batch": t_warm / t_cold,
+        "r1_warm_over_cold": [float(a / b) for a, b in zip(rwarm[:, 0], rcold[:, 0])],
+        "study_s": time.perf_counter() - t_all,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -318,6 +515,14 @@ def main():
                     help="continue both timed runs (untimed) to N iterations and compare "
                          "mixed with FP64 lift, drag and density (0: skip)")
     ap.add_argument("--no-warm-study", action="store_true")
+    ap.add_argument("--warm-study-large", action="store_true",
+                    help="also run the larger warm-start study (minutes of GPU time)")
+    ap.add_argument("--batch-drop-study", type=float, default=0, metavar="SCALE",
+                    help="also run the batched cases to each one's 1e-6 drop, on clouds SCALE "
+                         "times smaller (0: off)")
+    ap.add_argument("--batch-drop-max-iter", type=int, default=200000)
+    ap.add_argument("--batch-drop-no-sequential", action="store_true",
+                    help="skip the one-after-the-other comparison of that study")
     ap.add_argument("--no-fp64-data-mixed", action="store_true",
                     help="skip the mixed run whose q-derivative sweeps read FP64 data")
     ap.add_argument("--no-batch-study", action="store_true")
@@ -487,6 +692,20 @@ def main():
             out["batched"] = batch_study()
         except Exception as e:  # reported, never hides the throughput line
             out["batched"] = {"error": f"{type(e).__name__}: {e}"}
+    if args.batch_drop_study > 0:
+        log("batched cases to the drop")
+        try:
+            out["batched_to_drop"] = batch_drop_study(
+                args.batch_drop_study, args.batch_drop_max_iter,
+                sequential=not args.batch_drop_no_sequential)
+        except Exception as e:  # reported, never hides the throughput line
+            out["batched_to_drop"] = {"error": f"{type(e).__name__}: {e}"}
+    if args.warm_study_large:
+        log("larger warm-start study")
+        try:
+            out["warm_start_large"] = warm_study_large()
+        except Exception as e:  # reported, never hides the throughput line
+            out["warm_start_large"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_warm_study:
         log("warm-start study")
         try:

@@ -274,6 +274,14 @@ int ql_batch_info(const ql_solver *s, int32_t *ncase);
 int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_every, int32_t graph,
                  const double *ref_res, int32_t *iters_out, double *res_out);
 
+/* Progress of long batched runs: after every window of check_every
+ * iterations, ql_batch_run calls fn(user, iterations done, cases still
+ * active) on the calling thread, between windows (the device is idle for the
+ * call's duration; the callback must not call the library on this solver).
+ * fn = NULL turns it off.  Errors: QL_EINVAL (NULL solver). */
+typedef void (*ql_progress_fn)(void *user, int32_t iterations, int32_t active);
+int ql_set_progress(ql_solver *s, ql_progress_fn fn, void *user);
+
 /* Per-case outcome of the last ql_batch_run: status[c] = QL_OK (reached the
  * drop or ran max_iter), QL_EPOSITIVITY or QL_ENONFINITE (case c failed and
  * was retired), QL_EDIVERGED (its norm blew up).  status holds ncase entries (ql_batch_info); all QL_OK

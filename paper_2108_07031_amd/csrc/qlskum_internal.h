@@ -66,6 +66,11 @@ struct DevCloud {
     // conserved freestream of each case [ncase][4] (the kinetic outer
     // condition's far-field Maxwellian)
     const double *uinf;
+    // batched runs after retirements: the tiled sweeps launch one workgroup
+    // per entry of tile_list[ntile_live] (the tiles that still hold an
+    // active case, in tile order) instead of one per tile (null: every tile)
+    const int *tile_list;
+    int ntile_live;
 };
 
 struct FlowParams {
@@ -112,6 +117,8 @@ struct Retire {
 
 int num_blocks(int n);
 int num_flux_tiles(int n);
+// workgroups of a tiled sweep: one per tile, or per listed tile
+int sweep_grid(const DevCloud &c);
 
 // err_outer receives singular split stencils of outer points (used only by
 // the kinetic outer condition), err every other singular matrix.

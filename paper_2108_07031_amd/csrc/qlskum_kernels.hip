@@ -41,6 +41,12 @@ __device__ __forceinline__ int logical_block() {
 
 __device__ __forceinline__ int point_id() { return logical_block() * kBlock + threadIdx.x; }
 
+// tile served by this workgroup of a tiled sweep (launched with sweep_grid)
+__device__ __forceinline__ int sweep_tile(const DevCloud &cl) {
+    const int b = logical_block();
+    return cl.tile_list ? cl.tile_list[b] : b;
+}
+
 // The point and its code travel in one word, (p << 8) | code, so the
 // smallest failing point and the code it reported are always read together.
 __device__ __forceinline__ void report(ErrWord *err, int p, int code) {
@@ -554,7 +560,7 @@ __global__ void __launch_bounds__(kBlock) k_grad0(DevCloud cl, int cap,
                                                   Shadow sh) {
     constexpr int kRec = 3;
     extern __shared__ double2 lds[];
-    const int t = logical_block();
+    const int t = sweep_tile(cl);
     if (cl.tile_active && !cl.tile_active[t]) return;
     const TileInfo ti = tile_info(cl, t, cap);
     if (ti.in_lds) {
@@ -685,7 +691,7 @@ __global__ void __launch_bounds__(kBlock) k_gradk(DevCloud cl, int cap,
     constexpr int kRec = 5;
     extern __shared__ double2 lds[];
     uint16_t *eidx = reinterpret_cast<uint16_t *>(lds + (size_t)kRec * cap);
-    const int t = logical_block();
+    const int t = sweep_tile(cl);
     if (cl.tile_active && !cl.tile_active[t]) return;
     const TileInfo ti = tile_info(cl, t, cap);
     const int j = threadIdx.x / kFluxLanes, sub = threadIdx.x % kFluxLanes;
@@ -861,7 +867,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
                                                     float4 *__restrict__ qmm32, int want_bounds) {
     constexpr int kRec = 2;
     extern __shared__ double2 lds[];
-    const int t = logical_block();
+    const int t = sweep_tile(cl);
     if (cl.tile_active && !cl.tile_active[t]) return;
     const TileInfo ti = tile_info(cl, t, cap);
     if (ti.in_lds) {
@@ -925,7 +931,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
     constexpr int kRec = 3;
     extern __shared__ double2 lds[];
     uint16_t *eidx = reinterpret_cast<uint16_t *>(lds + (size_t)kRec * cap);
-    const int t = logical_block();
+    const int t = sweep_tile(cl);
     if (cl.tile_active && !cl.tile_active[t]) return;
     const TileInfo ti = tile_info(cl, t, cap);
     const int j = threadIdx.x / kFluxLanes, sub = threadIdx.x % kFluxLanes;
@@ -1013,7 +1019,7 @@ hipError_t launch_grad0(hipStream_t st, const DevCloud &c, int lds_budget, const
                         double2 *g, double2 *qmm, int want_bounds, Shadow sh) {
     const int rec = 3 * (int)sizeof(double2);
     const int cap = lds_cap(c, lds_budget > 0 ? lds_budget : kGrad0Lds, rec);
-    const int ntile = num_flux_tiles(c.n);
+    const int ntile = sweep_grid(c);
     if (want_bounds && !qmm) {
         if (!sh.qmm32) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_grad0<false>, dim3(ntile), dim3(kBlock), (size_t)cap * rec, st, c, cap,
@@ -1029,7 +1035,7 @@ hipError_t launch_grad0_f(hipStream_t st, const DevCloud &c, int lds_budget, con
                           float4 *g0f, float4 *qmm32, int want_bounds) {
     const int rec = 2 * (int)sizeof(double2);
     const int cap = lds_cap(c, lds_budget > 0 ? lds_budget : kGrad0FLds, rec);
-    hipLaunchKernelGGL(k_grad0_f, dim3(num_flux_tiles(c.n)), dim3(kBlock), (size_t)cap * rec, st,
+    hipLaunchKernelGGL(k_grad0_f, dim3(sweep_grid(c)), dim3(kBlock), (size_t)cap * rec, st,
                        c, cap, q32, g0f, qmm32, want_bounds);
     return hipGetLastError();
 }
@@ -1040,7 +1046,7 @@ hipError_t launch_gradk_f(hipStream_t st, const DevCloud &c, int lds_budget, con
     const int cap = min(lds_cap(c, lds_budget > 0 ? lds_budget : kGradkFLds, rec),
                         (kLdsBytes - 2 * kCapE) / rec);
     const size_t shmem = cap > 0 ? (size_t)cap * rec + 2 * kCapE : 0;
-    hipLaunchKernelGGL(k_gradk_f, dim3(num_flux_tiles(c.n)), dim3(kBlock), shmem, st, c, cap, g0f,
+    hipLaunchKernelGGL(k_gradk_f, dim3(sweep_grid(c)), dim3(kBlock), shmem, st, c, cap, g0f,
                        gprev, gnext);
     return hipGetLastError();
 }
@@ -1052,7 +1058,7 @@ hipError_t launch_gradk(hipStream_t st, const DevCloud &c, int lds_budget, const
     const int cap = min(lds_cap(c, lds_budget > 0 ? lds_budget : kGradkLds, rec),
                         (kLdsBytes - 2 * kCapE) / rec);
     const size_t shmem = cap > 0 ? (size_t)cap * rec + 2 * kCapE : 0;
-    hipLaunchKernelGGL(k_gradk, dim3(num_flux_tiles(c.n)), dim3(kBlock), shmem, st, c, cap, g0,
+    hipLaunchKernelGGL(k_gradk, dim3(sweep_grid(c)), dim3(kBlock), shmem, st, c, cap, g0,
                        gprev, gnext, g32);
     return hipGetLastError();
 }
@@ -1399,6 +1405,8 @@ __device__ __forceinline__ void rk_update(const DevCloud &cl, const FlowParams &
 // ---------------------------------------------------------------------------
 int num_flux_tiles(int n) { return (n + kFluxTile - 1) / kFluxTile; }
 
+int sweep_grid(const DevCloud &c) { return c.tile_list ? c.ntile_live : num_flux_tiles(c.n); }
+
 namespace {
 
 // Residual sums of live point p (slot j of its tile) over its entries
@@ -1506,7 +1514,7 @@ k_flux(DevCloud cl, FlowParams fp, int stage, int cap,
     constexpr int kRec = FIRST ? 3 : (LIMITER ? 11 : 7);
     extern __shared__ double2 lds[];
     const int n = cl.n;
-    const int t = logical_block();
+    const int t = sweep_tile(cl);
     if (cl.tile_active && !cl.tile_active[t]) return;
     if (cl.tile_prec && cl.tile_prec[t] != 0) return;  // an FP32-flux tile
     const int base = t * kFluxTile;
@@ -1624,7 +1632,7 @@ hipError_t launch_flux(hipStream_t st, const DevCloud &c, const FlowParams &fp, 
     const int rec = (first ? 3 : fp.limiter ? 11 : 7) * (int)sizeof(double2);
     const int cap = lds_cap(c, lds_budget, rec);
     const size_t shmem = (size_t)cap * rec;
-    const dim3 grid(num_flux_tiles(c.n)), block(kBlock);
+    const dim3 grid(sweep_grid(c)), block(kBlock);
     auto go = [&](auto kern, int stg, const double *rin, double *rout) {
         hipLaunchKernelGGL(kern, grid, block, shmem, st, c, fp, stg, cap, rin, q, g, qmm, U, Un,
                            dt, qnext, rout, q32next, err);
@@ -1950,7 +1958,7 @@ k_flux_mixed(
     extern __shared__ float4 ldsf[];
     double2 *lxy = reinterpret_cast<double2 *>(ldsf + (size_t)kRec * cap);
     const int n = cl.n;
-    const int t = logical_block();
+    const int t = sweep_tile(cl);
     if (cl.tile_active && !cl.tile_active[t]) return;
     if (cl.tile_prec && cl.tile_prec[t] != 1) return;  // an FP64-flux tile
     const int base = t * kFluxTile;
@@ -2032,7 +2040,7 @@ hipError_t launch_flux_mixed(hipStream_t st, const DevCloud &c, const FlowParams
     const int rec = ((first ? 1 : fp.limiter ? 5 : 3) + 1) * (int)sizeof(float4);
     const int cap = lds_cap(c, lds_budget, rec);
     const size_t shmem = (size_t)cap * rec;
-    const dim3 grid(num_flux_tiles(c.n)), block(kBlock);
+    const dim3 grid(sweep_grid(c)), block(kBlock);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, grid, block, shmem, st, c, fp, stage, cap, q, q32, g32, qmm32, U,
                            Un, dt, qnext, q32next, Rout, err);
@@ -2048,17 +2056,21 @@ hipError_t launch_flux_mixed(hipStream_t st, const DevCloud &c, const FlowParams
 
 // Residual norms per case, in a fixed summation order.  Points are split into
 // chunks that never straddle a case (chunk ch = [beg[ch], beg[ch+1])); one
-// workgroup sums R_c^2 over a chunk, then one workgroup adds each case's
-// chunk sums and writes sqrt(sum / updated points) into history row
-// (*ctr) and advances *ctr (replays of a captured iteration need no host
-// bookkeeping).  Held (outer without the kinetic outer condition) and
-// frozen points carry R = 0.
+// workgroup sums R_c^2 over a chunk, then one workgroup per case adds that
+// case's chunk sums and writes sqrt(sum / updated points) into history row
+// (*ctr), and *ctr advances (replays of a captured iteration need no host
+// bookkeeping).  Held (outer without the kinetic outer condition) points
+// carry R = 0.  In a batched run with retirement the chunks and the norms
+// of retired cases are skipped (their last norms are kept in rt.last).
 __global__ void __launch_bounds__(kBlock) k_res_chunks(const double *__restrict__ R, int n,
                                                        const int *__restrict__ beg,
-                                                       double *__restrict__ part) {
+                                                       double *__restrict__ part,
+                                                       const int *__restrict__ case_of,
+                                                       const uint8_t *__restrict__ active) {
     __shared__ double red[kBlock / 64][4];
     const int ch = blockIdx.x;
     const int b = beg[ch], e = beg[ch + 1];
+    if (active && b < e && !active[case_of[b]]) return;
     double acc[4] = {0, 0, 0, 0};
     for (int p = b + threadIdx.x; p < e; p += kBlock) {
 #pragma unroll
@@ -2092,7 +2104,10 @@ __global__ void __launch_bounds__(kBlock) k_res_cases(int ncase, const int *__re
     const int row = *ctr;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const double drop = rt.on ? *rt.drop : 0.0;
-    for (int cs = 0; cs < ncase; ++cs) {
+    // workgroup cs takes case cs (one workgroup: every case in turn, and it
+    // advances the row counter itself)
+    for (int cs = blockIdx.x; cs < ncase; cs += gridDim.x) {
+        if (rt.on && !rt.active[cs]) continue;
         double acc[4] = {0, 0, 0, 0};
         for (int j = chunk_ptr[cs] + threadIdx.x; j < chunk_ptr[cs + 1]; j += kBlock) {
 #pragma unroll
@@ -2130,8 +2145,11 @@ __global__ void __launch_bounds__(kBlock) k_res_cases(int ncase, const int *__re
                 rt.active[cs] = 0;
         }
     }
-    if (threadIdx.x == 0) *ctr = row + 1;
+    if (gridDim.x == 1 && threadIdx.x == 0) *ctr = row + 1;
 }
+
+// advances the history row counter after a k_res_cases of several workgroups
+__global__ void k_res_advance(int *ctr) { *ctr += 1; }
 
 // tile t is skipped by every tiled sweep when no case it holds is active;
 // its split fluxes are FP32 only while every case it holds is (case_prec
@@ -2158,9 +2176,11 @@ hipError_t launch_resnorm(hipStream_t st, const double *R, int n, int nchunk, co
                           double *part, int ncase, const int *chunk_ptr, const double *inv_nupd,
                           int *ctr, int cap, double *hist, const Retire &rt,
                           const int *case_of, uint8_t *tile_active, uint8_t *tile_prec) {
-    hipLaunchKernelGGL(k_res_chunks, dim3(nchunk), dim3(kBlock), 0, st, R, n, chunk_beg, part);
-    hipLaunchKernelGGL(k_res_cases, dim3(1), dim3(kBlock), 0, st, ncase, chunk_ptr, part,
+    hipLaunchKernelGGL(k_res_chunks, dim3(nchunk), dim3(kBlock), 0, st, R, n, chunk_beg, part,
+                       case_of, rt.on ? rt.active : nullptr);
+    hipLaunchKernelGGL(k_res_cases, dim3(ncase), dim3(kBlock), 0, st, ncase, chunk_ptr, part,
                        inv_nupd, ctr, cap, hist, rt);
+    if (ncase > 1) hipLaunchKernelGGL(k_res_advance, dim3(1), dim3(1), 0, st, ctr);
     if (rt.on) {
         const int ntile = num_flux_tiles(n);
         hipLaunchKernelGGL(k_tile_active, dim3((ntile + kBlock - 1) / kBlock), dim3(kBlock), 0, st,

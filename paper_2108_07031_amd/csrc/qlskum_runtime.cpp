@@ -80,6 +80,8 @@ struct ql_solver {
     float4 *q32[2] = {nullptr, nullptr}, *g32 = nullptr, *qmm32 = nullptr;  // FP32 shadows
     float4 *gf[3] = {nullptr, nullptr, nullptr};  // mixed q-derivatives: first pass, iterates
     bool grad_f32 = false;  // the last q-derivatives came from the FP32-data sweeps
+    ql_progress_fn progress = nullptr;  // batched-run progress callback
+    void *progress_user = nullptr;
     double *lsi = nullptr;
     double *Rpart[2] = {nullptr, nullptr};  // [4][n] partial sums of a split flux sweep
     int *fhalo_ptr = nullptr, *fhalo_idx = nullptr;  // tiles of kFluxTile points
@@ -114,6 +116,13 @@ struct ql_solver {
     int *bt_swit = nullptr;
     bool hybrid = false;  // iterations enqueued now run both flux kernels
     std::vector<int32_t> case_switch;  // per case, of the last ql_batch_run
+    // batched runs after retirements: the tiles still holding an active case
+    // (device list, its host source and length); the tiled sweeps enqueued
+    // while live_on is set launch over the list only
+    int *tile_list = nullptr;
+    std::vector<int> tile_list_h;
+    int ntile_live = 0;
+    bool live_on = false;
     // ql_step without a history: the iterations' status and last norms are
     // collected by the next call (rows of history written, and where)
     int step_pending = 0;
@@ -131,6 +140,7 @@ struct ql_solver {
     hipGraphExec_t graph = nullptr;
     int graph_qcur = -1;
     bool graph_hybrid = false;  // the captured iteration runs both flux kernels
+    int graph_live = 0;  // ... over this many listed tiles (0: every tile)
     bool capturing = false;
 
     bool timing = false;
@@ -186,7 +196,7 @@ void free_cloud(ql_solver *s) {
     dfree(s->gf[0]); dfree(s->gf[1]); dfree(s->gf[2]);
     dfree(s->case_of); dfree(s->chunk_beg); dfree(s->chunk_ptr); dfree(s->ctr);
     dfree(s->dwall_lo); dfree(s->wctr); dfree(s->wsel); dfree(s->wres);
-    dfree(s->case_active); dfree(s->tile_active); dfree(s->uinf); dfree(s->part);
+    dfree(s->case_active); dfree(s->tile_active); dfree(s->tile_list); dfree(s->uinf); dfree(s->part);
     dfree(s->inv_nupd); dfree(s->case_err); dfree(s->bt_ref); dfree(s->bt_last);
     dfree(s->bt_drop); dfree(s->bt_iters); dfree(s->case_prec); dfree(s->tile_prec);
     dfree(s->bt_switch); dfree(s->bt_swit);
@@ -385,6 +395,8 @@ DevCloud dev_cloud(const ql_solver *s) {
     c.uinf = s->uinf;
     c.case_err = s->case_err;
     c.tile_prec = s->hybrid ? s->tile_prec : nullptr;
+    c.tile_list = s->live_on ? s->tile_list : nullptr;
+    c.ntile_live = s->live_on ? s->ntile_live : 0;
     return c;
 }
 
@@ -675,7 +687,9 @@ int reset_counter(ql_solver *s) {
 // Capture one iteration into s->graph (rows of history: capacity per replay
 // block is reshist_cap / ncase).
 int capture_iteration(ql_solver *s) {
-    if (s->graph && s->graph_qcur == s->qcur && s->graph_hybrid == s->hybrid) return QL_OK;
+    if (s->graph && s->graph_qcur == s->qcur && s->graph_hybrid == s->hybrid &&
+        s->graph_live == (s->live_on ? s->ntile_live : 0))
+        return QL_OK;
     if (s->graph) (void)hipGraphExecDestroy(s->graph);
     s->graph = nullptr;
     const DevCloud c = dev_cloud(s);
@@ -699,6 +713,7 @@ int capture_iteration(ql_solver *s) {
     s->qcur = q0;  // capture enqueued nothing; the four stage flips cancel anyway
     s->graph_qcur = q0;
     s->graph_hybrid = s->hybrid;
+    s->graph_live = s->live_on ? s->ntile_live : 0;
     return QL_OK;
 }
 
@@ -989,6 +1004,7 @@ static int upload_impl(ql_solver *s, int32_t ncase, const int64_t *case_ptr, int
     s->case_err_clear.assign(ncase, kErrClear);
     HIPCHK(s, dalloc(&s->case_of, n)); HIPCHK(s, dalloc(&s->uinf, (size_t)4 * ncase));
     HIPCHK(s, dalloc(&s->case_active, ncase)); HIPCHK(s, dalloc(&s->tile_active, ntile));
+    HIPCHK(s, dalloc(&s->tile_list, ntile));
     HIPCHK(s, dalloc(&s->chunk_beg, nchunk + 1)); HIPCHK(s, dalloc(&s->chunk_ptr, ncase + 1));
     HIPCHK(s, dalloc(&s->part, (size_t)4 * nchunk)); HIPCHK(s, dalloc(&s->inv_nupd, 2 * ncase));
     HIPCHK(s, dalloc(&s->ctr, 1));
@@ -1647,6 +1663,13 @@ int ql_batch_status(const ql_solver *s, int32_t *status) {
     return QL_OK;
 }
 
+int ql_set_progress(ql_solver *s, ql_progress_fn fn, void *user) {
+    if (!s) return QL_EINVAL;
+    s->progress = fn;
+    s->progress_user = user;
+    return QL_OK;
+}
+
 int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_every, int32_t graph,
                  const double *ref_res, int32_t *iters_out, double *res_out) {
     int st = ensure_ready(s, true);
@@ -1698,13 +1721,13 @@ int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_ever
     }
     s->hybrid = hybrid;
     if ((st = reset_err(s)) || (st = reset_case_err(s))) return st;
-    const DevCloud c = dev_cloud(s);
     const FlowParams fp = flow_params(s);
     // the iterations enqueued below retire cases on the device at the
     // iteration they converge, diverge or fail; the host only looks between
     // windows of check_every iterations, to stop once no case is active
     s->retire_on = true;
-    int done = 0, nactive = nc;
+    s->live_on = false;
+    int done = 0, nactive = nc, listed = nc;
     while (done < max_iter && nactive > 0) {
         const int k = std::min(block, max_iter - done);
         if ((st = reset_counter(s))) break;
@@ -1715,7 +1738,8 @@ int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_ever
                     st = fail(s, QL_EDEVICE, "graph launch failed");
             if (st) break;
         } else {
-            for (int it = 0; it < k && !st; ++it) st = enqueue_iteration(s, c, fp, block, s->reshist);
+            const DevCloud cw = dev_cloud(s);
+            for (int it = 0; it < k && !st; ++it) st = enqueue_iteration(s, cw, fp, block, s->reshist);
             if (st) break;
         }
         HIPCHK(s, hipMemcpyAsync(active.data(), s->case_active, nc, hipMemcpyDeviceToHost,
@@ -1724,8 +1748,30 @@ int ql_batch_run(ql_solver *s, double drop, int32_t max_iter, int32_t check_ever
         harvest_timing(s);
         nactive = (int)std::count(active.begin(), active.end(), (uint8_t)1);
         done += k;
+        if (s->progress) s->progress(s->progress_user, done, nactive);
+        if (nactive > 0 && nactive < listed && done < max_iter) {
+            // cases retired in this window: from now on the tiled sweeps
+            // launch over the tiles that still hold an active case (tiles
+            // only ever leave the set during a run, and a listed tile that
+            // retires later is skipped by its tile_active flag as before)
+            tile.resize(ntile);
+            HIPCHK(s, hipMemcpyAsync(tile.data(), s->tile_active, ntile, hipMemcpyDeviceToHost,
+                                     s->stream));
+            HIPCHK(s, hipStreamSynchronize(s->stream));
+            s->tile_list_h.clear();
+            for (int t = 0; t < ntile; ++t)
+                if (tile[t]) s->tile_list_h.push_back(t);
+            if (s->tile_list_h.empty()) s->tile_list_h.push_back(0);
+            s->ntile_live = (int)s->tile_list_h.size();
+            HIPCHK(s, hipMemcpyAsync(s->tile_list, s->tile_list_h.data(),
+                                     sizeof(int) * s->tile_list_h.size(), hipMemcpyHostToDevice,
+                                     s->stream));
+            s->live_on = true;
+            listed = nactive;
+        }
     }
     s->retire_on = false;
+    s->live_on = false;
     s->hybrid = false;
     if (st) return st;
     if (hybrid)

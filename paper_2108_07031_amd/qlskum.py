@@ -31,7 +31,7 @@ EXPORTS = ("ql_default_params", "ql_create", "ql_destroy", "ql_upload_cloud", "q
            "ql_fetch_state", "ql_forces", "ql_last_error", "ql_evaluate", "ql_debug_fetch",
            "ql_debug_flags", "ql_cloud_size", "ql_set_timing", "ql_kernel_time",
            "ql_batch_upload", "ql_batch_info", "ql_batch_run", "ql_batch_status",
-           "ql_batch_switched",
+           "ql_batch_switched", "ql_set_progress",
            "ql_batch_forces",
            "ql_flux_tiles", "ql_mlp_create", "ql_mlp_destroy", "ql_mlp_last_error",
            "ql_mlp_num_params", "ql_mlp_set_weights", "ql_mlp_get_weights", "ql_mlp_forward",
@@ -52,6 +52,10 @@ class QLError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"qlskum error {code}: {msg}")
         self.code = code
+
+
+# void (*)(void *user, int32_t iterations, int32_t active)
+PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32)
 
 
 def _load():
@@ -102,6 +106,7 @@ def _load():
     lib.ql_autotune.argtypes = [vp, C.c_char_p, vp]
     lib.ql_batch_status.argtypes = [vp, vp]
     lib.ql_batch_switched.argtypes = [vp, vp]
+    lib.ql_set_progress.argtypes = [vp, PROGRESS_FN, vp]
     for name in EXPORTS:
         if name not in ("ql_default_params", "ql_last_error", "ql_mlp_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -255,6 +260,16 @@ def ql_batch_switched(s):
     out = np.zeros(ql_batch_info(s), np.int32)
     _check(s, lib.ql_batch_switched(s, out.ctypes.data))
     return out
+
+
+def ql_set_progress(s, fn):
+    """fn(iterations, active) after every check window of ql_batch_run, or
+    None; returns the ctypes callback, which must stay referenced while it
+    is set."""
+    cb = PROGRESS_FN(lambda _user, it, active: fn(int(it), int(active))) if fn else \
+        C.cast(None, PROGRESS_FN)
+    _check(s, lib.ql_set_progress(s, cb, None))
+    return cb
 
 
 def ql_autotune(s, cache_path=None):
@@ -539,6 +554,10 @@ class Solver:
 
     def batch_switched(self):
         return ql_batch_switched(self.h)
+
+    def set_progress(self, fn):
+        """fn(iterations, active) after every check window of batch_run."""
+        self._progress = ql_set_progress(self.h, fn)
 
     def wall_distance(self):
         return ql_wall_distance(self.h)

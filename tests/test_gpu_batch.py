@@ -297,3 +297,21 @@ def test_failed_case_retires_alone(ql, clouds, graph):
     s.batch_run(1e-300, 20, check_every=10, graph=graph)
     assert list(s.batch_status()) == [ql.QL_OK] * 3
     s.close()
+
+
+def test_progress_callback(ql):
+    """ql_set_progress: one call per check window with the iterations done so
+    far and the cases still active, the last at the run's end."""
+    _say("progress callback")
+    clouds = [naca_ocloud(48, 16), naca_ocloud(40, 16, tau=0.1)]
+    s = ql.Solver(limiter=0)
+    s.upload_batch(clouds, [0.63, 0.5], [2.0, 1.0])
+    s.init_freestream()
+    calls = []
+    s.set_progress(lambda it, active: calls.append((it, active)))
+    iters, _ = s.batch_run(1e-300, 250, check_every=100)
+    s.set_progress(None)
+    s.batch_run(1e-300, 10, check_every=5)
+    s.close()
+    assert calls == [(100, 2), (200, 2), (250, 2)], calls
+    assert list(iters) == [250, 250]
