@@ -36,9 +36,8 @@ def mixed_g_bound(c, q, g):
     over offsets no shorter than the smallest neighbour distance d_min by
     about 2^-23 max|q| / d_min; the factor 8 covers the stencils' geometry
     and the inner iterations (which contract).  q: (4, n), g: (8, n)."""
-    dmin = min(np.hypot(c.x[c.nbr_idx[c.nbr_ptr[p]:c.nbr_ptr[p + 1]]] - c.x[p],
-                        c.y[c.nbr_idx[c.nbr_ptr[p]:c.nbr_ptr[p + 1]]] - c.y[p]).min()
-               for p in range(c.n))
+    owner = np.repeat(np.arange(c.n), np.diff(c.nbr_ptr))
+    dmin = np.hypot(c.x[c.nbr_idx] - c.x[owner], c.y[c.nbr_idx] - c.y[owner]).min()
     qmax = np.abs(q).max(axis=1)
     return 8.0 * 2.0 ** -23 * np.concatenate([qmax, qmax]) / dmin / np.abs(g).max(axis=1)
 

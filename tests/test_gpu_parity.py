@@ -252,7 +252,7 @@ def test_error_paths(ql):
 def test_c2_full_size_evaluate(ql):
     """2.5M-point jittered cloud (1250 x 2000), M 0.85, alpha 1, limiter on:
     flags bit-exact, and one evaluation of the stage operator on every point
-    against the oracle.  On this cloud the near-wall split stencils are
+    against the oracle, in FP64 and (to the mixed bounds) in mixed precision.  On this cloud the near-wall split stencils are
     strongly anisotropic and their least-squares solves amplify rounding, so
     the bound is set from a measured noise floor: the distance between the
     oracle and the same oracle built with FMA contraction (two equally valid
@@ -273,6 +273,23 @@ def test_c2_full_size_evaluate(ql):
         err = normwise_rel(gpu[key], ora[key])
         _say(f"  {key}: gpu {err.max():.2e}  floor {floor.max():.2e}")
         assert np.all(err <= 10.0 * floor + 1e-14), (key, err, floor)
+    # mixed precision on the same cloud: q-derivatives within the bound of
+    # their FP32 data; R within the mixed evaluation bound (2e-3) or, where
+    # the cloud's conditioning is worse, within what the same conditioning
+    # makes of FP32 rounding: 10x the FP64 noise floor scaled by the ratio of
+    # the unit roundoffs, 2^-24 / 2^-53
+    sm = ql.Solver(c, precision=1, **prm)
+    sm.set_state(U)
+    mix = sm.evaluate()
+    sm.close()
+    gerr = normwise_rel(mix["g"], ora["g"])
+    gbound = mixed_g_bound(c, ora["q"], ora["g"])
+    rerr = normwise_rel(mix["R"], ora["R"])
+    rbound = np.maximum(2e-3, 10.0 * 2.0 ** 29 * normwise_rel(ora_fma["R"], ora["R"]))
+    _say(f"  mixed: g {gerr.max():.2e} (bound {gbound.min():.2e}), "
+         f"R {rerr.max():.2e} (bound {rbound.min():.2e})")
+    assert np.all(gerr <= gbound), (gerr, gbound)
+    assert np.all(rerr <= rbound), (rerr, rbound)
 
 
 def _sampled_iteration_check(c, U, Ugpu, prm, seed, count=48):
