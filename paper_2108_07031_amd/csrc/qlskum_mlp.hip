@@ -15,6 +15,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace ql {
 
 namespace {
@@ -115,6 +117,88 @@ hipError_t launch_mfma_gemm(hipStream_t st, int epi, bool a_kc, bool b_nc, int M
     else { QL_GEMM_EPI(false, false) }
 #undef QL_GEMM_EPI
 #undef QL_GEMM
+    return hipGetLastError();
+}
+
+// Split-K form of the plain product (kEpiStore) for few output blocks and a
+// long inner dimension -- the weight gradients a^T d, whose inner dimension
+// is the batch: wavefront (slice, block) sums one 16 x 16 block over the
+// kslice-long slice of K into part[slice][M][N], and k_gemm_reduce adds the
+// slices in slice order (a fixed order: results do not depend on timing).
+template <bool A_KC, bool B_NC>
+__global__ void __launch_bounds__(64 * kWaves)
+    k_mfma_gemm_splitk(int M, int N, int K, int kslice, const bf16 *__restrict__ A, int lda,
+                       const bf16 *__restrict__ B, int ldb, float *__restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int item = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const int ntn = (N + 15) / 16;
+    const int ntiles = ((M + 15) / 16) * ntn;
+    const int nsl = (K + kslice - 1) / kslice;
+    if (item >= ntiles * nsl) return;  // whole wavefront leaves together
+    const int sl = item / ntiles, tile = item % ntiles;
+    const int tm = tile / ntn, tn = tile % ntn;
+    const int r = tm * 16 + (lane & 15);
+    const int c = tn * 16 + (lane & 15);
+    const int kq = 8 * (lane >> 4);
+    const int kb = sl * kslice, ke = min(K, kb + kslice);
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = kb; k0 < ke; k0 += 32) {
+        const bf16x8 a = load_frag<A_KC>(A, lda, r, k0 + kq, M, ke);
+        const bf16x8 b = load_frag<B_NC>(B, ldb, c, k0 + kq, N, ke);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    }
+    const int n = tn * 16 + (lane & 15);
+    if (n >= N) return;
+    float *P = part + (size_t)sl * M * N;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int m = tm * 16 + 4 * (lane >> 4) + i;
+        if (m < M) P[(size_t)m * N + n] = acc[i];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_gemm_reduce(int M, int N, int nsl,
+                                                     const float *__restrict__ part,
+                                                     float *__restrict__ C, int ldc) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= M * N) return;
+    float s = 0.0f;
+    for (int sl = 0; sl < nsl; ++sl) s += part[(size_t)sl * M * N + idx];
+    C[(size_t)(idx / N) * ldc + idx % N] = s;
+}
+
+int gemm_splitk_slices(int M, int N, int K) {
+    const int tiles = ((M + 15) / 16) * ((N + 15) / 16);
+    if (tiles == 0 || tiles > kSplitKMaxTiles || K < 2 * kSplitKSlice) return 1;
+    return std::min(kSplitKMaxSlices, (K + kSplitKSlice - 1) / kSplitKSlice);
+}
+
+hipError_t launch_mfma_gemm_splitk(hipStream_t st, bool a_kc, bool b_nc, int M, int N, int K,
+                                   const bf16 *A, int lda, const bf16 *B, int ldb, float *part,
+                                   float *C32, int ldc) {
+    const int nsl = gemm_splitk_slices(M, N, K);
+    if (nsl <= 1)
+        return launch_mfma_gemm(st, kEpiStore, a_kc, b_nc, M, N, K, A, lda, B, ldb, nullptr,
+                                nullptr, C32, nullptr, ldc);
+    // slices of a whole number of 32-deep steps, nsl of them covering K
+    const int kslice = ((K + nsl - 1) / nsl + 31) / 32 * 32;
+    const int nsl_used = (K + kslice - 1) / kslice;
+    const int items = ((M + 15) / 16) * ((N + 15) / 16) * nsl_used;
+    const dim3 grid((items + kWaves - 1) / kWaves), block(64 * kWaves);
+    if (a_kc && b_nc)
+        hipLaunchKernelGGL((k_mfma_gemm_splitk<true, true>), grid, block, 0, st, M, N, K, kslice,
+                           A, lda, B, ldb, part);
+    else if (a_kc)
+        hipLaunchKernelGGL((k_mfma_gemm_splitk<true, false>), grid, block, 0, st, M, N, K, kslice,
+                           A, lda, B, ldb, part);
+    else if (b_nc)
+        hipLaunchKernelGGL((k_mfma_gemm_splitk<false, true>), grid, block, 0, st, M, N, K, kslice,
+                           A, lda, B, ldb, part);
+    else
+        hipLaunchKernelGGL((k_mfma_gemm_splitk<false, false>), grid, block, 0, st, M, N, K,
+                           kslice, A, lda, B, ldb, part);
+    hipLaunchKernelGGL(k_gemm_reduce, dim3((M * N + 255) / 256), dim3(256), 0, st, M, N, nsl_used,
+                       part, C32, ldc);
     return hipGetLastError();
 }
 

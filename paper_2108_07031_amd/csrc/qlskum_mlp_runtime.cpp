@@ -31,6 +31,7 @@ struct ql_mlp {
     float *y = nullptr;           // [max_batch][w_L]
     bf16 *d[2] = {nullptr, nullptr};
     float *part = nullptr, *loss = nullptr;
+    float *gpart = nullptr;  // split-K partial products of the weight gradients
     int64_t t = 0;  // Adam steps taken
     bool has_weights = false;
 };
@@ -117,9 +118,10 @@ int gradient(ql_mlp *m, const float *X, const float *T, int64_t n) {
     for (int l = L - 1; l >= 0; --l) {
         const int fi = m->widths[l], fo = m->widths[l + 1];
         float *gW = m->g + m->woff[l];
-        // dW_l = a_{l-1}^T d_l: op(A)(i, r) = act[r*fi + i], op(B)(r, j) = d[r*fo + j]
-        MCHK(m, launch_mfma_gemm(m->stream, kEpiStore, false, false, fi, fo, (int)n, m->act[l],
-                                 fi, m->d[cur], fo, nullptr, nullptr, gW, nullptr, fo));
+        // dW_l = a_{l-1}^T d_l: op(A)(i, r) = act[r*fi + i], op(B)(r, j) = d[r*fo + j];
+        // the inner dimension is the batch, so the product is split along it
+        MCHK(m, launch_mfma_gemm_splitk(m->stream, false, false, fi, fo, (int)n, m->act[l], fi,
+                                        m->d[cur], fo, m->gpart, gW, fo));
         MCHK(m, launch_colsum(m->stream, n, fo, m->d[cur], gW + (size_t)fi * fo));
         if (l > 0) {
             // d_{l-1} = (d_l W_l^T) * (1 - a_{l-1}^2): op(B)(j, i) = Wb[i*fo + j]
@@ -193,6 +195,12 @@ int ql_mlp_create(ql_mlp **out, int32_t device, void *hip_stream, const int32_t 
           malloc_n(&m->d[1], (size_t)max_batch * maxw) == hipSuccess &&
           malloc_n(&m->part, (size_t)((cnt + 255) / 256)) == hipSuccess &&
           malloc_n(&m->loss, 1) == hipSuccess;
+    size_t gp = 0;
+    for (int l = 0; l + 1 < nwidth; ++l) {
+        const int nsl = gemm_splitk_slices(widths[l], widths[l + 1], (int)max_batch);
+        if (nsl > 1) gp = std::max(gp, (size_t)nsl * widths[l] * widths[l + 1]);
+    }
+    okm = okm && (gp == 0 || malloc_n(&m->gpart, gp) == hipSuccess);
     if (!okm) {
         ql_mlp_destroy(m);
         return QL_ENOMEM;
@@ -210,6 +218,7 @@ int ql_mlp_destroy(ql_mlp *m) {
     for (auto &p : m->WbT) free_p(p);
     for (auto &p : m->act) free_p(p);
     free_p(m->y); free_p(m->d[0]); free_p(m->d[1]); free_p(m->part); free_p(m->loss);
+    free_p(m->gpart);
     if (m->own_stream && m->stream) (void)hipStreamDestroy(m->stream);
     delete m;
     return QL_OK;

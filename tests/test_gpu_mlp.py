@@ -54,8 +54,12 @@ def test_linear_layer_exact(env, K, N, n):
     m.close()
 
 
-@pytest.mark.parametrize("K,N,n", [(5, 4, 32), (6, 16, 64), (128, 128, 256), (37, 32, 64)])
+@pytest.mark.parametrize("K,N,n", [(5, 4, 32), (6, 16, 64), (128, 128, 256), (37, 32, 64),
+                                   (128, 128, 1024), (6, 4, 2048)])
 def test_linear_gradient_exact(env, K, N, n):
+    """n >= 512: the weight gradient's product is split along the batch
+    (slices of 256 rows added in slice order); on integer data every
+    partial sum is exact, so the result is the same bit for bit."""
     torch, ql = env
     _say(f"linear gradient K={K} N={N} n={n}")
     rng = np.random.default_rng(7 * K + N)
@@ -80,15 +84,18 @@ def _xavier(rng, widths):
     return np.concatenate(parts)
 
 
-def test_deep_network_matches_emulator(env):
+@pytest.mark.parametrize("n", [2048, 1500])
+def test_deep_network_matches_emulator(env, n):
+    """n = 1500: the split weight-gradient products end on a short slice
+    (six slices of 256 rows, the last of 220)."""
     torch, ql = env
-    _say("deep network forward and gradient")
+    _say(f"deep network forward and gradient, {n} rows")
     widths = [6, 128, 128, 128, 128, 4]
     rng = np.random.default_rng(2108)
     w = _xavier(rng, widths).astype(np.float32)
-    X = rng.normal(0.0, 1.0, (2048, 6)).astype(np.float32)
-    T = rng.normal(0.0, 1.0, (2048, 4)).astype(np.float32)
-    m = ql.Mlp(widths, max_batch=2048)
+    X = rng.normal(0.0, 1.0, (n, 6)).astype(np.float32)
+    T = rng.normal(0.0, 1.0, (n, 4)).astype(np.float32)
+    m = ql.Mlp(widths, max_batch=n)
     m.set_weights(w)
     assert m.num_params == 50948
     np.testing.assert_array_equal(m.get_weights(), w)
