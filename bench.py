@@ -37,10 +37,15 @@ FLOW = dict(mach=0.85, alpha_deg=1.0, limiter=1, venkat_k=5.0, cfl=0.2, n_inner=
 FP64_VALU_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak
 PREC_NAME = {0: "fp64", 1: "mixed"}
 
-# Algorithmic FP64 operations of the flux-residual kernel, per neighbour
+# Algorithmic FP64 operations of one flux-residual launch (one RK stage),
+# the roofline's unit: 940 per neighbour entry and point with the limiter,
+# 690 without (software transcendentals at 20-30 operations each), times
+# the cloud's mean neighbour count and its points.
+FLOPS_PER_ENTRY_UNIT = {1: 940, 0: 690}
+# An itemised count of the same launch, reported beside it: per neighbour
 # entry that enters at least one split stencil, and per split stencil it
-# enters; transcendentals and divides are counted at a fixed operation
-# cost (exp 20, log 20, erfc 30, sqrt 10, divide 10).
+# enters; transcendentals and divides at fixed costs (exp 20, log 20,
+# erfc 30, sqrt 10, divide 10).
 FLOPS_ENTRY_COMMON = 202       # geometry, reconstruction, two q~ -> primitive states
 FLOPS_ENTRY_LIMITER = 125      # Venkatakrishnan factors of 8 increments, eps^2
 FLOPS_PER_STENCIL = 191        # two split fluxes, their difference, weighted sum
@@ -85,8 +90,15 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def flux_flops_unit(n, nnz, limiter):
+    """Algorithmic FP64 operations of one flux-residual launch in the
+    roofline's unit: per point, FLOPS_PER_ENTRY_UNIT x the mean number of
+    neighbour entries."""
+    return FLOPS_PER_ENTRY_UNIT[1 if limiter else 0] * (nnz / n) * n  # (k_mean) x points
+
+
 def flux_flops_per_launch(flags, kind, ptr, limiter):
-    """Algorithmic FP64 operations of one flux-residual launch, from the
+    """Itemised FP64 operations of one flux-residual launch, from the
     library's split-membership flags (walls drop their n+ stencil; outer
     points carry no residual)."""
     npt = kind.shape[0]
@@ -622,7 +634,8 @@ def main():
         # the mixed path with FP64-data q-derivative sweeps, for comparison
         runs["mixed_grad1"] = timed_run(1, mixed_grad=1)
     head = runs[0] if 0 in runs else runs[1]
-    flops = flux_flops_per_launch(head["flags"], cloud.kind, cloud.nbr_ptr, FLOW["limiter"])
+    flops = flux_flops_unit(cloud.n, cloud.nnz, FLOW["limiter"])
+    flops_item = flux_flops_per_launch(head["flags"], cloud.kind, cloud.nbr_ptr, FLOW["limiter"])
     flux_ms, flux_cnt = head["ktime"][2]
     flux_avg_s = flux_ms / max(flux_cnt, 1) / 1e3
     achieved = flops / flux_avg_s / 1e12
@@ -656,7 +669,11 @@ def main():
             "frac": achieved / FP64_VALU_PEAK_TFLOPS,
             "traffic": committed_traffic(args.workload),
             "flops_per_launch": flops,
+            "flops_unit": f"{FLOPS_PER_ENTRY_UNIT[FLOW['limiter']]} x k_mean per point",
             "avg_launch_us": flux_avg_s * 1e6,
+            "itemised": {"flops_per_launch": flops_item,
+                         "achieved": flops_item / flux_avg_s / 1e12,
+                         "frac": flops_item / flux_avg_s / 1e12 / FP64_VALU_PEAK_TFLOPS},
         },
         "residual_first_last": [float(head["hist"][0, 0]), float(head["hist"][-1, 0])],
         "cl_cd": [head["cl"], head["cd"]],
