@@ -94,7 +94,7 @@ def flux_flops_unit(n, nnz, limiter):
     """Algorithmic FP64 operations of one flux-residual launch in the
     roofline's unit: per point, FLOPS_PER_ENTRY_UNIT x the mean number of
     neighbour entries."""
-    return FLOPS_PER_ENTRY_UNIT[1 if limiter else 0] * (nnz / n) * n  # (k_mean) x points
+    return int(round(FLOPS_PER_ENTRY_UNIT[1 if limiter else 0] * (nnz / n) * n))  # k_mean x n
 
 
 def flux_flops_per_launch(flags, kind, ptr, limiter):
