@@ -74,6 +74,38 @@ def test_mixed_evaluate_close_to_oracle(ql, limiter):
 
 
 @pytest.mark.parametrize("limiter", [0, 1])
+def test_mixed_iteration_pointwise(ql, limiter):
+    """One whole iteration from a smooth state, mixed against FP64, point by
+    point: each of the four stages moves a point by dt_p/2 R_p (the third
+    also averages with the start, which does not enlarge a difference), so
+    with the mixed residual within 2e-3 max|R_c| of the FP64 one (the
+    evaluation bound) every component of every point differs by at most
+    4 (dt_p/2) 2e-3 max|R_c|, doubled for the FP64 residual's own
+    dependence on the stage states (dt/2 |dR/dU| is about CFL/2)."""
+    _say(f"mixed iteration pointwise limiter={limiter}")
+    c = cloud("c1")
+    prm = dict(limiter=limiter, mach=0.85 if limiter else 0.63, alpha_deg=1.0 if limiter else 2.0)
+    U = smooth_state(c, mach=prm["mach"], alpha_deg=prm["alpha_deg"])
+    s64 = ql.Solver(c, precision=0, **prm)
+    s64.set_state(U)
+    e64 = s64.evaluate()
+    s64.set_state(U)
+    s64.step(1)
+    U64 = s64.fetch_state()
+    s64.close()
+    s32 = ql.Solver(c, precision=1, **prm)
+    s32.set_state(U)
+    s32.step(1)
+    U32 = s32.fetch_state()
+    s32.close()
+    rmax = np.abs(e64["R"]).max(axis=1)
+    bound = 4.0 * e64["dt"][None, :] * 2e-3 * rmax[:, None] + 1e-15 * np.abs(U64)
+    ratio = (np.abs(U32 - U64) / np.maximum(bound, 1e-300)).max()
+    _say(f"  largest difference / bound {ratio:.3f}")
+    assert np.all(np.abs(U32 - U64) <= bound), ratio
+
+
+@pytest.mark.parametrize("limiter", [0, 1])
 def test_mixed_grad_fp64_data(ql, limiter):
     """mixed_grad 1: the q-derivative sweeps read FP64 data, so the mixed
     path's q-derivatives equal the FP64 path's bit for bit (both run the FP64
