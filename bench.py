@@ -112,7 +112,7 @@ def flux_flops_per_launch(flags, kind, ptr, limiter):
     return int(used.sum()) * common + int(stencils.sum()) * FLOPS_PER_STENCIL
 
 
-def cpu_baseline(cloud, budget_s=15.0, max_iter=10):
+def cpu_baseline(cloud, budget_s=30.0, max_iter=10):
     """The oracle as it stands on a bounded sample of the same workload.
     Main figure: the OpenMP build of the oracle (results bit for bit the
     serial build's) on every host thread it is given (OMP_NUM_THREADS),
