@@ -259,8 +259,10 @@ int ql_batch_info(const ql_solver *s, int32_t *ncase);
  * iteration m leaves, which is the state of ql_step(m) from the same start,
  * and iters_out[c] = m.  Its points stop updating and workgroups holding
  * only retired points skip every sweep, while the other cases go on.  The
- * host reads the active flags every check_every iterations only to stop
- * once none is left.  graph != 0 captures one iteration into a hipGraph on
+ * host reads the active flags every check_every iterations to stop once
+ * none is left; after a window in which cases retired, the tiled sweeps
+ * are launched over the tiles that still hold an active case only (the
+ * results are the same bit for bit).  graph != 0 captures one iteration into a hipGraph on
  * the solver's stream (re-captured after parameter or buffer changes) and
  * replays it.  iters_out[c] (nullable) receives the iterations case c ran,
  * res_out[c][4] (nullable) the norms of its last one.
