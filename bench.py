@@ -12,6 +12,7 @@ Prints one JSON line (see the repository's measurement notes for the
 roofline and CPU-baseline definitions).
 """
 import argparse
+import functools
 import hashlib
 import json
 import os
@@ -217,6 +218,24 @@ def _batch_clouds(scale):
     return conds, clouds
 
 
+def _progress_logger(tag, every=10000):
+    """A progress callback for batched runs (called by the library after each
+    check window): logs when the number of active cases changes, and every
+    `every` iterations, with the seconds since start() was called."""
+    state = {"active": None, "t0": time.perf_counter()}
+
+    def fn(it, active):
+        if active != state["active"] or it % every == 0:
+            log(f"    {tag}: iteration {it}, {active} cases active "
+                f"({time.perf_counter() - state['t0']:.1f} s)")
+            state["active"] = active
+
+    def start():
+        state["t0"] = time.perf_counter()
+    fn.start = start
+    return fn
+
+
 def batch_drop_study(scale, max_iter, check_every=500, switch=3e-5, sequential=True):
     """The batched form run to each case's 1e-6 drop of its first residual:
     mixed precision with the precision switch, one batch (captured iteration
@@ -232,17 +251,11 @@ def batch_drop_study(scale, max_iter, check_every=500, switch=3e-5, sequential=T
     s = ql.Solver(**prm)
     s.upload_batch(clouds, [c["mach"] for c in conds], [c["alpha"] for c in conds])
     s.init_freestream()
-    seen = {"active": len(clouds), "t0": 0.0}
-
-    def progress(it, active, every=10000):
-        # from the batched run's own check windows
-        if active != seen["active"] or it % every == 0:
-            log(f"    iteration {it}: {active} cases active "
-                f"({time.perf_counter() - seen['t0']:.1f} s)")
-            seen["active"] = active
+    progress = _progress_logger("batch")
     s.set_progress(progress)
     torch.cuda.synchronize()
-    t0 = seen["t0"] = time.perf_counter()
+    progress.start()
+    t0 = time.perf_counter()
     iters, _ = s.batch_run(1e-6, max_iter, check_every=check_every)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
@@ -254,8 +267,7 @@ def batch_drop_study(scale, max_iter, check_every=500, switch=3e-5, sequential=T
     for k, (cl, c) in enumerate(zip(clouds, conds) if sequential else ()):
         so = ql.Solver(cl, mach=c["mach"], alpha_deg=c["alpha"], **prm)
         so.init_freestream()
-        so.set_progress(lambda it, active, k=k: it % 20000 == 0 and
-                        log(f"    case {k}: iteration {it}"))
+        so.set_progress(_progress_logger(f"case {k}", every=20000))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         it, _ = so.batch_run(1e-6, max_iter, check_every=check_every)
@@ -268,7 +280,7 @@ def batch_drop_study(scale, max_iter, check_every=500, switch=3e-5, sequential=T
     work = float(sum(cl.n * int(i) for cl, i in zip(clouds, iters)))
     return {"cases": len(clouds), "points_total": total, "scale": scale,
             "points_min_max": [min(cl.n for cl in clouds), max(cl.n for cl in clouds)],
-            "precision": "mixed, switch to FP64 fluxes at 3e-5 of the first residual",
+            "precision": f"mixed, switch to FP64 fluxes at {switch:g} of the first residual",
             "drop": 1e-6, "max_iter": max_iter,
             "reached": int(sum(1 for st, i in zip(status, iters)
                                if st == ql.QL_OK and i < max_iter)),
@@ -423,14 +435,7 @@ def warm_study_large():
     tclouds = [naca_ocloud(W["ns_test"], W["nr_test"], tau=c["tau"], jitter=0.1, seed=1000 + k)
                for k, c in enumerate(test)]
 
-    def progress(tag):
-        seen = {"active": None}
-
-        def fn(it, active):
-            if active != seen["active"] or it % 20000 == 0:
-                log(f"    {tag}: iteration {it}, {active} cases active")
-                seen["active"] = active
-        return fn
+    progress = functools.partial(_progress_logger, every=20000)
     s = ql.Solver(**prm)
     offs = s.upload_batch(clouds, [c["mach"] for c in train], [c["alpha"] for c in train])
     s.set_progress(progress("training solve"))
@@ -499,7 +504,7 @@ def warm_study_large():
         "cases_train": W["n_train"], "points_per_train_case": clouds[0].n,
         "cases_test": W["n_test"], "points_per_test_case": tclouds[0].n,
         "mach_range": list(W["mach"]), "drop": W["drop"], "max_iter": W["max_iter"],
-        "precision": "mixed, switch to FP64 fluxes at 3e-5 of the first residual",
+        "precision": f"mixed, switch to FP64 fluxes at {W['switch']:g} of the first residual",
         "train_converged": int(np.sum(ok_case)), "train_samples": int(keep.sum()),
         "train_solve_s": t_conv, "train_net_s": t_train, "train_loss": loss,
         "network": "6-128x4-4 tanh, bf16 MFMA, FP32 accumulate, Adam",
