@@ -791,7 +791,8 @@ __device__ __forceinline__ void grad0f_entries(const DevCloud &cl, const double2
                                                const double qp[4], double2 P, double sx[4],
                                                double sy[4], float mx[4], float mn[4]) {
     constexpr int kRec = 2;
-#pragma unroll 1
+    // two entries in flight per lane (each lane's sums keep their order)
+#pragma unroll 2
     for (int k = k0 + sub; k < k1; k += kFluxLanes) {
         float4 a;
         double2 Q;
@@ -861,7 +862,7 @@ __device__ __forceinline__ double2 lane_pair(const float4 *g, int p, int sub) {
 
 }  // namespace
 
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) k_grad0_f(DevCloud cl, int cap,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) k_grad0_f(DevCloud cl, int cap,
                                                     const float4 *__restrict__ q32,
                                                     float4 *__restrict__ g0f,
                                                     float4 *__restrict__ qmm32, int want_bounds) {
@@ -1009,9 +1010,11 @@ static int lds_cap(const DevCloud &c, int budget, int rec) {
 // than 36 KB, although a few more tiles then read from memory).
 constexpr int kGrad0Lds = 32 * 1024;
 constexpr int kGradkLds = 22 * 1024;
-// The FP32-data sweeps fit 64 VGPRs, i.e. 8 waves per SIMD: 8 workgroups
-// per CU when each stays within 20 KB of LDS (images of 32- and 48-byte
-// records; the inner iteration's 4 KB of entry slots come on top).
+// The FP32-data inner iteration fits 64 VGPRs, i.e. 8 waves per SIMD: 8
+// workgroups per CU when each stays within 20 KB of LDS (images of 48-byte
+// records plus 4 KB of entry slots).  The first pass keeps two entries in
+// flight per lane at 72 VGPRs (7 waves); its images of 32-byte records fit
+// 20 KB as well.
 constexpr int kGrad0FLds = 20 * 1024;
 constexpr int kGradkFLds = 20 * 1024 - 2 * kCapE;
 
