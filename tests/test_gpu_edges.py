@@ -6,7 +6,8 @@ rejected with a status and a message that names the point or entry, and
 the solver stays usable for a valid upload afterwards.  A cloud whose last
 64-point tile is partly filled matches the oracle like the full-tile
 clouds: one evaluation to the evaluation tolerances, 30 iterations to
-1e-11 per state component.
+1e-11 per state component.  Out-of-range parameters are refused and leave
+the solver usable.
 """
 import ctypes as C
 
@@ -126,3 +127,24 @@ def test_ragged_tile_parity(ql, limiter):
     _say(f"  30 iterations: {err}")
     assert np.all(err <= 1e-11), err
     s.close()
+
+
+def test_parameter_rejections(ql):
+    """Out-of-range parameters are refused by ql_set_params with QL_EINVAL
+    and leave the solver's parameters as they were; NULL solvers are refused
+    by the progress setter."""
+    _say("parameter rejections")
+    c = naca_ocloud(48, 16)
+    s = ql.Solver(c, precision=1)
+    for bad in (dict(mixed_grad=2), dict(mixed_grad=-1), dict(mixed_switch=1.0),
+                dict(mixed_switch=-1e-3), dict(precision=2), dict(grad_lds=200 * 1024),
+                dict(n_inner=-1), dict(cfl=0.0), dict(outer_bc=2), dict(flux_split=3)):
+        with pytest.raises(ql.QLError) as e:
+            s.set_params(**bad)
+        assert e.value.code == ql.QL_EINVAL, bad
+    # still usable with the parameters it had
+    s.init_freestream()
+    h = s.step(3)
+    assert np.all(np.isfinite(h))
+    s.close()
+    assert ql.lib.ql_set_progress(None, ql.PROGRESS_FN(), None) == ql.QL_EINVAL
